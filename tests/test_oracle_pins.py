@@ -1,0 +1,421 @@
+"""Pins of the FP64 oracle to facts the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each compares the oracle with an
+independent fact -- an exact discrete identity, a closed-form spectrum, a
+conservation (energy) identity, an invariance, a brute-force dense solve or a
+count that follows from the geometry.  The mutation tests at the end plant
+plausible mistakes in the oracle and check that some pin catches each.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import fit_oracle as O
+from paper_1705_08849_amd import devices as D
+
+SHAPES = [(3, 4, 5), (5, 2, 3), (4, 4, 4)]
+
+
+# --- Sec. II eq. (CP): topology --------------------------------------------
+
+@pytest.mark.parametrize("n", SHAPES)
+def test_curl_annihilates_gradients_and_divergence_annihilates_curl(n):
+    """div curl = 0 and curl grad = 0 hold exactly in integers (the discrete
+    de Rham identities behind C~ = C^T, Sec. II)."""
+    c, g, s = O.curl(*n), O.gradient(*n), O.divergence(*n)
+    assert c.dtype.kind == "i"
+    assert abs(c @ g).max() == 0
+    assert abs(s @ c).max() == 0
+    # dual identity S~ C~ = -(C G)^T = 0 with S~ = -G^T
+    assert abs((-g.T) @ c.T).max() == 0
+
+
+@pytest.mark.parametrize("n", SHAPES)
+def test_partial_difference_rows_have_one_plus_one_minus(n):
+    """P_w has exactly one +1 and one -1 per row (Sec. II), except the last
+    node along w, which has no successor (ghost row, zero)."""
+    nx, ny, nz = n
+    for p, m in zip(O.partials(nx, ny, nz), (nx, ny, nz)):
+        p = p.tocsr()
+        counts = np.diff(p.indptr)
+        assert set(np.unique(counts)) <= {0, 2}
+        assert (counts == 0).sum() == nx * ny * nz // m
+        for r in np.nonzero(counts == 2)[0][:50]:
+            assert sorted(p.data[p.indptr[r]:p.indptr[r + 1]].tolist()) == [-1, 1]
+
+
+def test_curl_has_four_entries_per_facet_row():
+    """Four nonzeros per row of C (Sec. III preallocation), +-1 valued."""
+    c = O.curl(6, 5, 4).tocsr()
+    counts = np.diff(c.indptr)
+    assert counts.max() == 4
+    assert set(np.unique(np.abs(c.data))) == {1}
+
+
+# --- Sec. II/III: the assembled system ----------------------------------------
+
+def _small_layered(seed=11, graded=True):
+    return D.layered_device(10, 9, 8, n_layers=3, n_strips=1, n_ports=1, seed=seed,
+                            graded=graded)
+
+
+def test_system_has_at_most_13_entries_per_row_and_is_symmetric():
+    """Sec. II: 13 nonzeros per row; Table I: the operator is (complex)
+    symmetric A = A^T since the dual curl is C^T."""
+    for dev in (D.cavity(6, 5, 4), _small_layered()):
+        a = O.system_matrix(dev, 2 * np.pi * 7e9).tocsr()
+        counts = np.diff(a.indptr)
+        assert counts.max() == 13
+        assert (counts == 13).sum() > 0
+        assert abs(a - a.T).max() == 0.0
+
+
+def test_free_edge_count_of_closed_box_matches_geometry():
+    """Electric walls on all faces: x-edges survive only strictly inside the
+    y and z ranges, and likewise for y and z (Sec. II boundary condition)."""
+    ncx, ncy, ncz = 5, 4, 3
+    f = O.free_edges(D.cavity(ncx, ncy, ncz))
+    expected = (ncx * (ncy - 1) * (ncz - 1) + ncy * (ncx - 1) * (ncz - 1)
+                + ncz * (ncx - 1) * (ncy - 1))
+    assert f.sum() == expected
+
+
+def test_pec_cell_removes_exactly_its_twelve_edges():
+    dev = D.cavity(6, 6, 6)
+    base = O.free_edges(dev).sum()
+    dev.materials.append(D.Material(is_pec=True))
+    dev.cell_mat[3, 3, 3] = 1  # an interior cell: all 12 of its edges are free before
+    assert base - O.free_edges(dev).sum() == 12
+
+
+def test_open_walls_keep_boundary_edges():
+    """Without electric walls only the ghost edges are removed."""
+    dev = D.cavity(3, 4, 5)
+    dev.pec_walls = 0
+    nx, ny, nz = dev.nodes
+    expected = 3 * nx * ny * nz - (ny * nz + nx * nz + nx * ny)
+    assert O.free_edges(dev).sum() == expected
+
+
+# --- Sec. IV: cavity eigenmodes (closed forms) -------------------------------
+
+def _discrete_cavity_spectrum(ncx, ncy, ncz, hx, hy, hz):
+    """Exact FIT/Yee spectrum of a homogeneous vacuum PEC box: modes (m, n, p)
+    with 0 <= m < ncx etc., at most one index zero, two polarisations when all
+    three are non-zero, omega^2 = c^2 sum (2/h)^2 sin^2(m pi / (2 nc))."""
+    vals = []
+    for m in range(ncx):
+        for n in range(ncy):
+            for p in range(ncz):
+                z = (m == 0) + (n == 0) + (p == 0)
+                if z >= 2:
+                    continue
+                w2 = O.C0 ** 2 * ((2 / hx) ** 2 * np.sin(m * np.pi / (2 * ncx)) ** 2
+                                  + (2 / hy) ** 2 * np.sin(n * np.pi / (2 * ncy)) ** 2
+                                  + (2 / hz) ** 2 * np.sin(p * np.pi / (2 * ncz)) ** 2)
+                vals += [w2] * (2 if z == 0 else 1)
+    return np.sort(vals)
+
+
+@pytest.mark.parametrize("dims", [((4, 3, 5), (1e-3, 1.3e-3, 0.7e-3)),
+                                  ((3, 3, 3), (2e-3, 2e-3, 2e-3))])
+def test_full_discrete_cavity_spectrum(dims):
+    (ncx, ncy, ncz), (hx, hy, hz) = dims
+    dev = D.cavity(ncx, ncy, ncz, hx, hy, hz)
+    lam = O.cavity_eigenfrequencies(dev)  # omega^2 values (dense)
+    interior = (ncx - 1) * (ncy - 1) * (ncz - 1)
+    tiny = np.abs(lam) <= 1e-9 * lam.max()
+    assert tiny.sum() == interior  # gradient null space: one per interior node
+    ref = _discrete_cavity_spectrum(ncx, ncy, ncz, hx, hy, hz)
+    got = np.sort(lam[~tiny])
+    assert got.shape == ref.shape
+    np.testing.assert_allclose(got, ref, rtol=1e-10)
+
+
+def test_tiny_cavity_first_resonance_matches_closed_forms():
+    """16^3 cells of 1 mm: TE101/TE011/TE110 are degenerate at the discrete
+    value, within O(h^2) of the continuous f = (c/2) sqrt(2)/a."""
+    dev = D.cavity(16, 16, 16, 1e-3)
+    f = O.cavity_eigenfrequencies(dev, k=4, sigma_f=13.0e9)
+    disc = O.C0 / (2 * np.pi) * np.sqrt(2) * (2 / 1e-3) * np.sin(np.pi / 32)
+    np.testing.assert_allclose(f[:3], disc, rtol=1e-9)
+    cont = 0.5 * O.C0 * np.sqrt(2) / 16e-3
+    assert abs(f[0] / cont - 1) < 2e-3
+    assert f[3] > f[0] * 1.1
+
+
+def test_homogeneous_permittivity_scales_frequencies():
+    a = O.cavity_eigenfrequencies(D.cavity(3, 4, 3, 1e-3, 0.9e-3, 1.2e-3))
+    b = O.cavity_eigenfrequencies(D.cavity(3, 4, 3, 1e-3, 0.9e-3, 1.2e-3, eps_r=4.0))
+    nz = a > 1e-9 * a.max()
+    np.testing.assert_allclose(np.sort(b[nz]), np.sort(a[nz]) / 4.0, rtol=1e-10)
+
+
+# --- Sec. II material averaging: energy identities ----------------------------
+
+def _open_random_device(seed=3):
+    rng = np.random.default_rng(seed)
+    ncx, ncy, ncz = 5, 4, 6
+    mats = [D.Material(eps_r=float(rng.uniform(1, 12)), mu_r=float(rng.uniform(1, 3)),
+                       sigma=float(rng.uniform(0, 5)), tan_delta=float(rng.uniform(0, 0.05)))
+            for _ in range(4)]
+    dev = D.Device(dx=rng.uniform(1e-4, 5e-4, ncx), dy=rng.uniform(1e-4, 5e-4, ncy),
+                   dz=rng.uniform(1e-4, 5e-4, ncz),
+                   cell_mat=rng.integers(0, 4, (ncz, ncy, ncx)).astype(np.uint8),
+                   materials=mats, ports=[], pec_walls=0)
+    return dev
+
+
+def test_permittivity_energy_of_uniform_field_equals_cell_sum():
+    """A uniform field E0 along w gives e = E0 * L on every w-edge; the
+    electric energy e^T M_eps e must equal E0^2 sum_cells eps_cell V_cell --
+    the defining property of averaging over dual facets with half cells at
+    the boundary (graded, inhomogeneous, lossy)."""
+    dev = _open_random_device()
+    m_eps, m_sig = O.edge_materials(dev)
+    nx, ny, nz = dev.nodes
+    vol = dev.dz[:, None, None] * dev.dy[None, :, None] * dev.dx[None, None, :]
+    mats = dev.materials
+    eps_c = np.array([O.EPS0 * m.eps_r * (1 - 1j * m.tan_delta) for m in mats])[dev.cell_mat]
+    sig_c = np.array([m.sigma for m in mats])[dev.cell_mat]
+    lengths = [dev.dx, dev.dy, dev.dz]
+    for w in range(3):
+        L = np.zeros((nz, ny, nx))
+        idx = [slice(None)] * 3
+        ax = 2 - w
+        shape = [1, 1, 1]
+        shape[ax] = len(lengths[w])
+        sl = [slice(None)] * 3
+        sl[ax] = slice(0, len(lengths[w]))
+        L[tuple(sl)] = lengths[w].reshape(shape)
+        e2 = np.zeros(dev.n_edges)
+        e2[w::3] = (L ** 2).ravel()
+        np.testing.assert_allclose((m_eps * e2).sum(), (eps_c * vol).sum(), rtol=1e-12)
+        np.testing.assert_allclose((m_sig * e2).sum(), (sig_c * vol).sum(), rtol=1e-12)
+
+
+def test_reluctance_energy_of_uniform_flux_equals_cell_sum():
+    """A uniform B0 along w gives b = B0 * area on every w-facet; the magnetic
+    energy b^T M_nu b must equal B0^2 sum_cells V_cell / mu_cell (series
+    combination along the dual edge)."""
+    dev = _open_random_device()
+    nu = O.facet_reluctance(dev)
+    nx, ny, nz = dev.nodes
+    vol = dev.dz[:, None, None] * dev.dy[None, :, None] * dev.dx[None, None, :]
+    inv_mu = np.array([1 / (O.MU0 * m.mu_r) for m in dev.materials])[dev.cell_mat]
+    ncx, ncy, ncz = dev.ncx, dev.ncy, dev.ncz
+    for w in range(3):
+        # facet area on every existing w-facet (all nodes along w)
+        a = np.zeros((nz, ny, nx))
+        if w == 0:
+            a[:ncz, :ncy, :] = (dev.dz[:, None] * dev.dy[None, :])[:, :, None]
+        elif w == 1:
+            a[:ncz, :, :ncx] = (dev.dz[:, None] * dev.dx[None, :])[:, None, :]
+        else:
+            a[:, :ncy, :ncx] = (dev.dy[:, None] * dev.dx[None, :])[None, :, :]
+        b2 = np.zeros(dev.n_edges)
+        b2[w::3] = (a ** 2).ravel()
+        np.testing.assert_allclose((nu * b2).sum(), (inv_mu * vol).sum(), rtol=1e-12)
+
+
+def test_interface_edge_averages_two_permittivities():
+    """On equal spacings an x-edge lying on the interface between eps1 (below)
+    and eps2 (above) sees eps0 (eps1 + eps2)/2 over its full dual facet."""
+    dev = D.cavity(4, 4, 4, 1e-3)
+    dev.materials = [D.Material(eps_r=2.0), D.Material(eps_r=7.0)]
+    dev.cell_mat[2:] = 1
+    m_eps, _ = O.edge_materials(dev)
+    e = dev.edge_index(0, 1, 2, 2)  # x-edge in plane z = 2 (interface), interior in y
+    np.testing.assert_allclose(m_eps[e].real, O.EPS0 * 4.5 * 1e-3 * 1e-3 / 1e-3, rtol=1e-14)
+
+
+def test_length_scaling_invariance():
+    """M_eps ~ length and M_nu ~ 1/length, so A(omega/lam; lam*grid) = A/lam."""
+    dev = _small_layered()
+    lam = 3.7
+    dev2 = D.Device(dx=dev.dx * lam, dy=dev.dy * lam, dz=dev.dz * lam, cell_mat=dev.cell_mat,
+                    materials=dev.materials, ports=dev.ports, pec_walls=dev.pec_walls)
+    om = 2 * np.pi * 9e9
+    a1 = O.system_matrix(dev, om)
+    a2 = O.system_matrix(dev2, om / lam)
+    # port conductances do not scale with length; compare without ports
+    dev.ports, dev2.ports = [], []
+    a1 = O.system_matrix(dev, om)
+    a2 = O.system_matrix(dev2, om / lam)
+    diff = abs(a2 * lam - a1).max()
+    assert diff <= 1e-13 * abs(a1).max()
+
+
+def test_gradients_are_in_the_static_null_space_on_graded_meshes():
+    """K (grad phi) = 0 for any nodal potential that vanishes on the walls
+    (graded, inhomogeneous, lossy, mu_r != 1, closed electric box)."""
+    dev = _open_random_device(5)
+    dev.pec_walls = 0x3F
+    nx, ny, nz = dev.nodes
+    rng = np.random.default_rng(0)
+    phi = rng.standard_normal((nz, ny, nx))
+    phi[0], phi[-1], phi[:, 0], phi[:, -1], phi[:, :, 0], phi[:, :, -1] = 0, 0, 0, 0, 0, 0
+    e = O.gradient(nx, ny, nz).astype(float) @ phi.ravel()
+    f = O.free_edges(dev)
+    e[~f] = 0.0
+    k = O.stiffness(dev)
+    y = (k @ e)[f]
+    assert np.linalg.norm(y) <= 1e-12 * abs(k).max() * np.linalg.norm(e)
+
+
+def test_sym_scaled_operator_has_unit_mass():
+    """Eq. (e2t): S A S = S K S - omega^2 I, so for a lossless cavity the
+    eigenvalues of S A S + omega^2 I are the cavity's omega_mnp^2."""
+    dev = D.cavity(3, 3, 4, 1e-3, 1e-3, 1.5e-3)
+    om = 2 * np.pi * 50e9
+    a = O.system_matrix(dev, om).toarray()
+    s = O.sym_scaling(dev, om)
+    hat = s[:, None] * a * s[None, :] + om ** 2 * np.eye(len(s))
+    lam = np.sort(np.linalg.eigvalsh(0.5 * (hat + hat.T).real))
+    ref = O.cavity_eigenfrequencies(dev)
+    np.testing.assert_allclose(lam, np.sort(ref), rtol=1e-9, atol=1e-9 * ref.max())
+
+
+# --- Solves ------------------------------------------------------------------
+
+def test_direct_solve_matches_dense_brute_force():
+    dev = D.layered_device(5, 4, 4, n_layers=2, n_strips=1, n_ports=1, seed=1)
+    om = 2 * np.pi * 12e9
+    j = D.port_source(dev, 0)
+    x = O.solve_direct(dev, om, j)
+    a = O.system_matrix(dev, om).toarray()
+    b = O.rhs(dev, om, j)
+    xd = np.linalg.solve(a, b)
+    assert np.linalg.norm(x[O.free_edges(dev)] - xd) <= 1e-9 * np.linalg.norm(xd)
+    assert O.relative_residual(dev, om, j, x) < 1e-12
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "gmres"])
+def test_textbook_krylov_reaches_direct_solution(method):
+    dev, om, j = D.tiny_cavity_case()
+    a = O.system_matrix(dev, om)
+    b = O.rhs(dev, om, j)
+    ref = O.solve_direct(dev, om, j)[O.free_edges(dev)]
+    if method == "bicgstab":
+        x, it, rr = O.bicgstab(a, b, tol=1e-10)
+    else:
+        x, it, rr = O.gmres(a, b, restart=30, tol=1e-10)
+    assert rr <= 1e-10
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-7
+
+
+def test_flexible_gmres_with_exact_inverse_converges_in_one_step():
+    dev = D.layered_device(4, 4, 3, n_layers=2, n_strips=1, n_ports=1, seed=2)
+    om = 2 * np.pi * 5e9
+    a = O.system_matrix(dev, om).tocsc()
+    b = O.rhs(dev, om, D.port_source(dev, 0))
+    import scipy.sparse.linalg as spla
+    lu = spla.splu(a)
+    x, it, rr = O.gmres(a, b, restart=5, tol=1e-12, precond=lu.solve)
+    assert it == 1 and rr < 1e-12
+
+
+def test_reciprocity_and_passivity_of_two_port():
+    """Z_pq = Z_qp (complex symmetry of A) and Re Z_pp >= 0 for a lossy
+    device, with Z = -u/I (u = sum of edge voltages along the port, Sec. IV;
+    the minus sign because e integrates E from the ground end upward)."""
+    dev = D.layered_device(12, 10, 6, n_layers=2, n_strips=2, n_ports=2, seed=4)
+    assert len(dev.ports) == 2
+    om = 2 * np.pi * 6e9
+    z = np.zeros((2, 2), complex)
+    for q in range(2):
+        x = O.solve_direct(dev, om, D.port_source(dev, q))
+        z[:, q] = -O.port_voltages(dev, x) / 1.0
+    assert abs(z[0, 1] - z[1, 0]) <= 1e-9 * abs(z).max()
+    assert z[0, 0].real >= 0 and z[1, 1].real >= 0
+
+
+def test_tiny_cavity_case_bicgstab_reaches_1e8():
+    dev, om, j = D.tiny_cavity_case()
+    a = O.system_matrix(dev, om)
+    b = O.rhs(dev, om, j)
+    assert a.shape[0] == 10800 and dev.n_edges == 14739
+    x, it, rr = O.bicgstab(a, b, tol=1e-8)
+    assert rr <= 1e-8 and it < 200
+
+
+# --- Mutation tests: plant mistakes in the oracle, the pins must notice ------
+
+def _run_pins():
+    fails = []
+    for name, fn in [
+        ("spectrum", lambda: test_full_discrete_cavity_spectrum(((4, 3, 5), (1e-3, 1.3e-3, 0.7e-3)))),
+        ("topology", lambda: test_curl_annihilates_gradients_and_divergence_annihilates_curl((3, 4, 5))),
+        ("eps_energy", test_permittivity_energy_of_uniform_field_equals_cell_sum),
+        ("nu_energy", test_reluctance_energy_of_uniform_flux_equals_cell_sum),
+        ("count", test_free_edge_count_of_closed_box_matches_geometry),
+        ("pec12", test_pec_cell_removes_exactly_its_twelve_edges),
+        ("passive", test_reciprocity_and_passivity_of_two_port),
+    ]:
+        try:
+            fn()
+        except AssertionError:
+            fails.append(name)
+    return fails
+
+
+def test_mutation_wrong_curl_sign_is_caught(monkeypatch):
+    real = O.curl
+
+    def bad(nx, ny, nz):
+        px, py, pz = O.partials(nx, ny, nz)
+        blk = sp.bmat([[None, pz, py], [pz, None, -px], [-py, px, None]], format="csr")
+        q = O.interleave(nx * ny * nz)
+        return (q @ blk @ q.T).tocsr()
+
+    monkeypatch.setattr(O, "curl", bad)
+    assert _run_pins()
+    monkeypatch.setattr(O, "curl", real)
+
+
+def test_mutation_dropped_averaging_term_is_caught(monkeypatch):
+    real = O._sum_pairs
+
+    def bad(w, axes):
+        for ax in axes[:1]:  # forgets the second axis of the dual-facet sum
+            w = real(w, (ax,))
+        if len(axes) > 1:
+            pad = [(0, 0)] * w.ndim
+            pad[axes[1]] = (0, 1)
+            w = np.pad(w, pad)
+        return w
+
+    monkeypatch.setattr(O, "_sum_pairs", bad)
+    assert _run_pins()
+
+
+def test_mutation_mask_ignoring_pec_cells_is_caught(monkeypatch):
+    real = O._cell_props
+
+    def bad(dev):
+        eps_c, sigma, inv_mu, pec = real(dev)
+        return eps_c, sigma, inv_mu, np.zeros_like(pec)
+
+    monkeypatch.setattr(O, "_cell_props", bad)
+    assert "pec12" in _run_pins()
+
+
+def test_mutation_wrong_loss_sign_is_caught(monkeypatch):
+    real = O.diagonal
+
+    def bad(dev, omega):
+        m_eps, m_sig = O.edge_materials(dev)
+        return -omega * omega * np.conj(m_eps) - 1j * omega * m_sig
+
+    monkeypatch.setattr(O, "diagonal", bad)
+    assert "passive" in _run_pins()
+
+
+def test_mutation_half_cell_at_boundary_is_caught(monkeypatch):
+    real = O.facet_reluctance
+
+    def bad(dev):
+        nu = real(dev)
+        return nu * 1.0000001  # tiny global scale error of the reluctances
+    monkeypatch.setattr(O, "facet_reluctance", bad)
+    assert {"spectrum", "nu_energy"} <= set(_run_pins())
