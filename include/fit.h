@@ -1,0 +1,290 @@
+/*
+ * fit.h -- C ABI of the MI355X matrix-free frequency-domain FIT library.
+ *
+ * The library applies and inverts the complex curl-curl operator of the
+ * Finite Integration Technique,
+ *
+ *     A(omega) = C^T M_nu C  -  omega^2 M_eps  +  j omega M_sigma,
+ *
+ * (Geranmayeh, Sec. II: grid equations, eq. (CP) for the curl C with
+ * dual curl C^T, eq. (Material) for the diagonal material matrices, eq. (e2)
+ * for the wave equation with s = j*omega) on a non-equidistant Cartesian
+ * primal/dual grid pair, without ever storing A, C or the material diagonals:
+ * every entry is recomputed from the cell spacings and a per-cell material
+ * id each time the operator is applied (Sec. III, the matrix-free operator of
+ * eq. (e2t)).  Around the operator it runs the Krylov methods the paper
+ * compares (Sec. IV: BiCGStab, restarted GMRES, flexible GMRES) to a
+ * relative residual tolerance.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Time factor e^{+j omega t}; the right-hand side of eq. (e2) is
+ *    b = -j omega j, where j is the impressed current per edge [A].  The
+ *    unknown e is the edge voltage [V].
+ *  - Unknown ordering is the paper's cell-by-cell interleaving (Sec. II,
+ *    eq. (e12Nxyz)): with Nx = ncx+1, Ny = ncy+1, Nz = ncz+1 primal nodes,
+ *    edge (w, i, j, k), w = 0/1/2 for x/y/z, is element
+ *        3 * (i + Nx * (j + Ny * k)) + w
+ *    of an n_e = 3 Nx Ny Nz vector.  Edges that do not exist (ghost edges at
+ *    the upper end of an axis), edges tangential to an electric wall and
+ *    edges touching a PEC cell are "masked": they carry no unknown.
+ *  - Complex vectors are interleaved (re, im): complex128 = 2 doubles,
+ *    complex64 = 2 floats per element.  Device buffers are owned by the
+ *    caller, live on the grid's device, are contiguous and at least 16-byte
+ *    aligned (8-byte for complex64).
+ *  - Streams are hipStream_t passed as void*; NULL means the null stream.
+ *  - Every call returns a fit_status; nothing throws or aborts across the
+ *    ABI.  fit_last_error() returns a thread-local description of the most
+ *    recent failure on the calling thread.
+ */
+#ifndef FIT_H
+#define FIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FIT_OK = 0,
+  FIT_E_INVALID = 1,       /* bad argument; nothing was written */
+  FIT_E_NOMEM = 2,         /* device or host allocation failed */
+  FIT_E_DEVICE = 3,        /* a HIP runtime call failed */
+  FIT_E_NOT_CONVERGED = 4, /* iteration cap reached; best iterate returned */
+  FIT_E_BREAKDOWN = 5,     /* Krylov breakdown not cured by restarts */
+  FIT_E_NAN = 6,           /* NaN/Inf met in the iteration */
+  FIT_E_UNSUPPORTED = 7
+} fit_status;
+
+typedef enum { FIT_C128 = 0, FIT_C64 = 1 } fit_dtype;
+
+/* FIT_SCALE_NONE: y = A(omega) x, the operator of eq. (e2) with losses.
+ * FIT_SCALE_SYM:  y = S A(omega) S x with S = diag(M_eps,c^{-1/2}),
+ *   M_eps,c = M_eps - j M_sigma / omega: the symmetrically scaled operator of
+ *   eqs. (e2s)/(e2t), S C^T M_nu C S - omega^2 I.  Requires omega > 0. */
+typedef enum { FIT_SCALE_NONE = 0, FIT_SCALE_SYM = 1 } fit_scaling;
+
+typedef enum { FIT_BICGSTAB = 0, FIT_GMRES = 1, FIT_FGMRES = 2 } fit_solver;
+
+/* FIT_PREC_FP64:  complex128 operator and Krylov vectors throughout.
+ * FIT_PREC_MIXED: complex64 operator and inner Krylov iterations, complex128
+ *   outer residual r = b - A x, solution update and stopping test
+ *   (iterative refinement). */
+typedef enum { FIT_PREC_FP64 = 0, FIT_PREC_MIXED = 1 } fit_precision;
+
+/* One material (Sec. II, eq. (Material); complex permittivity for dielectric
+ * losses eps0 eps_r (1 - j tan_delta); conductivity sigma [S/m]). */
+typedef struct {
+  double eps_r;
+  double mu_r;
+  double sigma;
+  double tan_delta;
+  int32_t is_pec; /* nonzero: perfect electric conductor cell */
+  int32_t reserved;
+} fit_material;
+
+/* Lumped port (Sec. IV): the z-edges (i, j, k) with k0 <= k < k1.  The port
+ * drives equal currents through its edges and loads them with an internal
+ * impedance z0 [Ohm] split evenly over the k1-k0 edges (each edge gets a
+ * conductance (k1-k0)/z0). */
+typedef struct {
+  int32_t i, j, k0, k1;
+  double z0;
+} fit_port;
+
+/* Grid description; all pointers are host pointers and are copied by
+ * fit_grid_create (the caller may free them afterwards). */
+typedef struct {
+  int32_t ncx, ncy, ncz;    /* cells per axis, each >= 1 */
+  int32_t nmat;             /* 1 <= nmat <= 254 */
+  const double *dx;         /* ncx cell widths [m], > 0 */
+  const double *dy;         /* ncy */
+  const double *dz;         /* ncz */
+  const uint8_t *cell_mat;  /* ncx*ncy*ncz ids < nmat; cell (a,b,c) at a + ncx*(b + ncy*c) */
+  const fit_material *mats; /* nmat entries */
+  int32_t nports;           /* 0 <= nports <= 64 */
+  uint32_t pec_walls;       /* electric walls, bits -x,+x,-y,+y,-z,+z (0x3F: closed box) */
+  const fit_port *ports;    /* nports entries; at most one port per (i, j) column */
+} fit_grid_desc;
+
+struct fit_grid;
+struct fit_precond;
+
+typedef struct {
+  int32_t solver;      /* fit_solver */
+  int32_t restart;     /* GMRES/FGMRES restart length m, 1..64 (0 -> 30) */
+  int32_t max_iters;   /* cap on Krylov iterations (BiCGStab: iterations of two
+                          operator applications; GMRES: Arnoldi steps); 0 -> 100000 */
+  int32_t check_every; /* host polls the device convergence flag every this many
+                          iterations (0 -> automatic) */
+  int32_t precision;   /* fit_precision */
+  int32_t scaling;     /* fit_scaling the Krylov iteration works in internally;
+                          the stopping test always uses the unscaled system */
+  double inner_tol;    /* FIT_PREC_MIXED: relative tolerance of each inner solve
+                          (0 -> 1e-4) */
+  struct fit_precond *precond; /* FIT_FGMRES: learned right preconditioner, or NULL */
+  void *stream;        /* hipStream_t for all work of the call */
+  double *resid_history; /* optional host array: recursive residual estimate
+                            (relative) after each iteration */
+  int32_t resid_history_len;
+  int32_t use_graph;   /* nonzero: replay captured hipGraphs of check_every
+                          iterations instead of eager launches */
+} fit_solve_opts;
+
+typedef struct {
+  int32_t status;       /* fit_status of the call */
+  int32_t iterations;   /* Krylov iterations performed (inner ones for MIXED) */
+  int32_t refinements;  /* outer refinement steps (MIXED) or true-residual restarts */
+  int32_t fell_back;    /* preconditioner or precision fallback taken */
+  int32_t matvecs;      /* operator applications (all precisions) */
+  int32_t reserved;
+  double true_relres;   /* ||b - A x||_2 / ||b||_2, unscaled, complex128 */
+  double time_ms;       /* wall time of the call */
+  double bytes_moved;   /* algorithmic HBM bytes of the kernels launched */
+} fit_solve_info;
+
+/* Validate a grid description and upload it to device `device`.
+ * Errors: FIT_E_INVALID (sizes < 1, non-positive or non-finite spacing,
+ * material id >= nmat, nmat outside 1..254, port outside the grid or two ports
+ * on one column), FIT_E_DEVICE, FIT_E_NOMEM.  On success *out owns device
+ * copies of the geometry; release with fit_grid_destroy. */
+fit_status fit_grid_create(const fit_grid_desc *desc, int device, struct fit_grid **out);
+
+/* Release a grid (NULL-safe).  Waits for nothing: the caller must have
+ * synchronised work that uses it. */
+void fit_grid_destroy(struct fit_grid *g);
+
+/* n_e = 3 Nx Ny Nz, or -1 for NULL. */
+int64_t fit_num_edges(const struct fit_grid *g);
+
+/* Boundary condition of Sec. II: write 1 for every edge that carries an
+ * unknown (exists, not tangential to an electric wall, touches no PEC cell)
+ * and 0 otherwise into the n_e-byte device buffer mask_dev.  Asynchronous on
+ * `stream`. */
+fit_status fit_edge_mask(const struct fit_grid *g, uint8_t *mask_dev, void *stream);
+
+/* Material diagonals as recomputed on the fly by the operator (debug/test):
+ *   kind 0: M_eps per edge (complex: eps averaged over the dual facet / length)
+ *   kind 1: M_sigma per edge including port conductances (real part only)
+ *   kind 2: M_nu = M_mu^{-1} per primal facet (facet (w,i,j,k) at the edge
+ *           index formula), real part only
+ * Written as complex128 into out_dev (n_e elements), for every index
+ * including masked and ghost ones.  Asynchronous on `stream`. */
+fit_status fit_material_diag(const struct fit_grid *g, int kind, double *out_dev, void *stream);
+
+/* y = A(omega) x (or S A S x for FIT_SCALE_SYM) in the given precision.
+ * x_dev, y_dev: n_e complex elements of dtype; they must not overlap.
+ * y is 0 on masked edges and x is ignored there.  Asynchronous on `stream`.
+ * Errors: FIT_E_INVALID (NULL pointers, omega < 0, SYM with omega == 0). */
+fit_status fit_matvec(const struct fit_grid *g, double omega, int dtype, int scaling,
+                      const void *x_dev, void *y_dev, void *stream);
+
+/* Batched operator: for b in [0, nbatch), y_b = A(omegas[b]) x_b, with the
+ * nbatch vectors stored back to back (x_dev + b*n_e elements).  omegas is a
+ * host array.  Reads the grid's materials once per tile for all systems.
+ * Asynchronous on `stream`; 1 <= nbatch <= 64. */
+fit_status fit_matvec_batched(const struct fit_grid *g, int nbatch, const double *omegas,
+                              int dtype, int scaling, const void *x_dev, void *y_dev,
+                              void *stream);
+
+/* Solve A(omega) e = -j omega j for e (Sec. II eq. (e2), Sec. IV) with the
+ * Krylov method in opts, from e = 0, until the unscaled complex128 relative
+ * residual ||b - A e|| / ||b|| <= tol.
+ * source_dev: impressed current j, n_e complex128 on the device; must be zero
+ *   on masked edges (else FIT_E_INVALID).
+ * x_dev: output e, n_e complex128 (0 on masked edges).
+ * info: optional, filled on every return except FIT_E_INVALID.
+ * FIT_E_NOT_CONVERGED / FIT_E_BREAKDOWN / FIT_E_NAN still return the best
+ * iterate.  Synchronous: returns after the stream has drained. */
+fit_status fit_solve(struct fit_grid *g, double omega, const void *source_dev, double tol,
+                     const fit_solve_opts *opts, void *x_dev, fit_solve_info *info);
+
+/* Frequency and right-hand-side sweep over several grids (Sec. II: each
+ * frequency is an independent system; Sec. IV: multi-port excitation).
+ * For every grid g, omega index f and right-hand side r, solves
+ * A_g(omegas[f]) e = -j omegas[f] j_{g,r} with all systems advanced together
+ * in batched launches replayed from captured hipGraphs, complex64 inner
+ * iterations and complex128 refinement (opts->precision is honoured).
+ *   sources_dev[g]: nrhs * n_e(g) complex128 device buffer (rhs r at r*n_e).
+ *   port_v_host:    [g][f][r][p] complex128 (2 doubles) port voltages, the sum
+ *                   of edge voltages over port p of grid g (Sec. IV probes);
+ *                   p runs over that grid's nports, so the block of grid g has
+ *                   nomega*nrhs*nports(g) entries, grids back to back.
+ *   x_dev_opt:      NULL, or per grid a nomega*nrhs*n_e complex128 buffer for
+ *                   the fields.
+ *   infos:          ngrids*nomega*nrhs entries, or NULL.
+ * Synchronous.  Returns FIT_OK only if every system met tol. */
+fit_status fit_sweep(struct fit_grid *const *grids, int ngrids, const double *omegas, int nomega,
+                     const void *const *sources_dev, int nrhs, double tol,
+                     const fit_solve_opts *opts, double *port_v_host, void *const *x_dev_opt,
+                     fit_solve_info *infos);
+
+/* Sum of edge voltages over each port of g for `nvec` complex128 fields
+ * stored back to back on the device; writes nvec*nports complex128 values
+ * (2 doubles each) to the host array out_host.  Synchronous. */
+fit_status fit_port_voltages(const struct fit_grid *g, const void *x_dev, int nvec,
+                             double *out_host, void *stream);
+
+/* ---- stencil launch shapes and the autotuner ------------------------------
+ * The operator kernels tile the node grid into TX x TY columns marching up
+ * ZC z-planes.  Compiled shapes: (TX, TY) in {(64,4), (64,8), (32,8)}.  The
+ * table is process-wide and keyed by the grid's node dimensions and dtype. */
+
+/* Force a tile shape for grids of g's node dimensions in `dtype`.
+ * FIT_E_INVALID for a shape that is not compiled or zc < 1. */
+fit_status fit_tile_set(const struct fit_grid *g, int dtype, int tx, int ty, int zc);
+
+/* Time every compiled (TX, TY) with a range of ZC on g (operator in `dtype`
+ * and `scaling` at omega, `reps` timed launches each, HIP events on `stream`),
+ * record the fastest in the table and report it.  best_us: mean kernel time of
+ * the winner.  Synchronous; allocates two scratch vectors. */
+fit_status fit_autotune(const struct fit_grid *g, int dtype, int scaling, double omega, int reps,
+                        void *stream, int32_t *tx, int32_t *ty, int32_t *zc, double *best_us);
+
+/* Write / read the tile table as JSON ({"entries": [{"nx":..,"ny":..,"nz":..,
+ * "dtype":..,"tx":..,"ty":..,"zc":..,"us":..}, ...], "arch": "gfx950"}). */
+fit_status fit_tune_save(const char *path);
+fit_status fit_tune_load(const char *path);
+
+/* ---- learned right preconditioner (3-level 3D U-Net, BF16 MFMA) ---------- */
+
+/* Training configuration for fit_precond_train (all fields have defaults
+ * when 0). */
+typedef struct {
+  int32_t base_channels; /* channels of the first level (16) */
+  int32_t steps;         /* optimiser steps (2000) */
+  int32_t batch;         /* crops per step (4) */
+  int32_t crop;          /* crop edge in nodes, multiple of 4 (32) */
+  int32_t pairs_per_system; /* residual->error pairs harvested per system (200) */
+  int32_t seed;
+  double lr;             /* Adam learning rate (1e-3) */
+  double weight_decay;
+  void *stream;
+} fit_precond_cfg;
+
+/* Train a preconditioner on residual->error pairs generated by plain solves on
+ * the given grids and frequencies.  Synchronous. */
+fit_status fit_precond_train(struct fit_grid *const *train, int ntrain, const double *omegas,
+                             int nomega, const fit_precond_cfg *cfg, struct fit_precond **out);
+/* Create an untrained (randomly initialised, seeded) preconditioner. */
+fit_status fit_precond_create(const fit_precond_cfg *cfg, int device, struct fit_precond **out);
+/* Serialise (blob NULL: only report the size in *n) / deserialise weights. */
+fit_status fit_precond_save(const struct fit_precond *p, void *blob, size_t *n);
+fit_status fit_precond_load(const void *blob, size_t n, int device, struct fit_precond **out);
+/* z = M(v) for one complex128 vector on grid g at omega (what FGMRES calls). */
+fit_status fit_precond_apply(struct fit_precond *p, const struct fit_grid *g, double omega,
+                             const void *v_dev, void *z_dev, void *stream);
+void fit_precond_destroy(struct fit_precond *p);
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char *fit_last_error(void);
+
+/* Library version string. */
+const char *fit_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIT_H */

@@ -1,0 +1,45 @@
+// Entry points declared in fit.h whose implementation has not landed yet.
+// Each reports FIT_E_UNSUPPORTED with a message.
+#include "fit_internal.h"
+
+using namespace fit;
+
+static fit_status unsupported(const char* name) {
+  set_error(std::string(name) + ": not implemented in this build");
+  return FIT_E_UNSUPPORTED;
+}
+
+extern "C" fit_status fit_matvec_batched(const fit_grid*, int, const double*, int, int, const void*,
+                                         void*, void*) {
+  return unsupported("fit_matvec_batched");
+}
+extern "C" fit_status fit_solve(fit_grid*, double, const void*, double, const fit_solve_opts*, void*,
+                                fit_solve_info*) {
+  return unsupported("fit_solve");
+}
+extern "C" fit_status fit_sweep(fit_grid* const*, int, const double*, int, const void* const*, int,
+                                double, const fit_solve_opts*, double*, void* const*,
+                                fit_solve_info*) {
+  return unsupported("fit_sweep");
+}
+extern "C" fit_status fit_port_voltages(const fit_grid*, const void*, int, double*, void*) {
+  return unsupported("fit_port_voltages");
+}
+extern "C" fit_status fit_precond_train(fit_grid* const*, int, const double*, int,
+                                        const fit_precond_cfg*, fit_precond**) {
+  return unsupported("fit_precond_train");
+}
+extern "C" fit_status fit_precond_create(const fit_precond_cfg*, int, fit_precond**) {
+  return unsupported("fit_precond_create");
+}
+extern "C" fit_status fit_precond_save(const fit_precond*, void*, size_t*) {
+  return unsupported("fit_precond_save");
+}
+extern "C" fit_status fit_precond_load(const void*, size_t, int, fit_precond**) {
+  return unsupported("fit_precond_load");
+}
+extern "C" fit_status fit_precond_apply(fit_precond*, const fit_grid*, double, const void*, void*,
+                                        void*) {
+  return unsupported("fit_precond_apply");
+}
+extern "C" void fit_precond_destroy(fit_precond*) {}

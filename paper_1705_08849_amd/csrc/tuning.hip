@@ -1,0 +1,223 @@
+// Tile-shape table, defaults and the on-device autotuner.
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <tuple>
+#include <vector>
+
+#include "tuning.h"
+
+namespace fit {
+
+namespace {
+struct TunedEntry {
+  TileShape t;
+  double us;
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, TunedEntry> g_tuned;  // (nx, ny, nz, dtype)
+}  // namespace
+
+TileShape default_tile(const GridView& g, int dtype) {
+  (void)dtype;
+  TileShape t{64, 4, 16};
+  const long nbx = (g.nx + t.tx - 1) / t.tx, nby = (g.ny + t.ty - 1) / t.ty;
+  const long cols = nbx * nby;
+  int zc = g.nz;
+  const long target = 1024;  // ~4 workgroups per CU on 256 CUs
+  while (zc > 8 && cols * ((g.nz + zc - 1) / zc) < target) zc = (zc + 1) / 2;
+  t.zc = zc < 1 ? 1 : zc;
+  return t;
+}
+
+TileShape tile_for(const fit_grid* g, int dtype) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(std::make_tuple(g->view.nx, g->view.ny, g->view.nz, dtype));
+  if (it != g_tuned.end()) return it->second.t;
+  return default_tile(g->view, dtype);
+}
+
+static void record_tile(const GridView& g, int dtype, TileShape t, double us) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[std::make_tuple(g.nx, g.ny, g.nz, dtype)] = TunedEntry{t, us};
+}
+
+template <class T>
+static fit_status time_shape(const fit_grid* g, TileShape t, int scaling, double omega, int reps,
+                             const void* x, void* y, hipStream_t s, double* us) {
+  OpMatvec<T> op{(const T*)x, (T*)y};
+  auto launch = [&]() {
+    return scaling == FIT_SCALE_SYM ? launch_stencil<T, MODE_MEC>(g->view, t, omega, op, s)
+                                    : launch_stencil<T, MODE_D>(g->view, t, omega, op, s);
+  };
+  fit_status st;
+  for (int w = 0; w < 2; ++w)
+    if ((st = launch()) != FIT_OK) return st;
+  hipEvent_t e0, e1;
+  FIT_HIP(hipEventCreate(&e0));
+  FIT_HIP(hipEventCreate(&e1));
+  FIT_HIP(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r)
+    if ((st = launch()) != FIT_OK) return st;
+  FIT_HIP(hipEventRecord(e1, s));
+  FIT_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  FIT_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us = 1000.0 * ms / reps;
+  return FIT_OK;
+}
+
+}  // namespace fit
+
+using namespace fit;
+
+extern "C" fit_status fit_tile_set(const fit_grid* g, int dtype, int tx, int ty, int zc) {
+  if (!g || (dtype != FIT_C128 && dtype != FIT_C64)) {
+    set_error("fit_tile_set: NULL grid or bad dtype");
+    return FIT_E_INVALID;
+  }
+  TileShape t{tx, ty, zc};
+  if (!tile_supported(t)) {
+    set_error("fit_tile_set: shape not compiled (TX,TY in {(64,4),(64,8),(32,8)}, zc >= 1)");
+    return FIT_E_INVALID;
+  }
+  record_tile(g->view, dtype, t, 0.0);
+  return FIT_OK;
+}
+
+extern "C" fit_status fit_autotune(const fit_grid* g, int dtype, int scaling, double omega,
+                                   int reps, void* stream, int32_t* tx, int32_t* ty, int32_t* zc,
+                                   double* best_us) {
+  if (!g || (dtype != FIT_C128 && dtype != FIT_C64) || reps < 1 ||
+      (scaling != FIT_SCALE_NONE && scaling != FIT_SCALE_SYM) ||
+      (scaling == FIT_SCALE_SYM && !(omega > 0.0))) {
+    set_error("fit_autotune: bad argument");
+    return FIT_E_INVALID;
+  }
+  DeviceScope dev(g->device);
+  const size_t bytes = (size_t)g->ne * (dtype == FIT_C128 ? 16 : 8);
+  void *x = nullptr, *y = nullptr;
+  FIT_HIP(hipMalloc(&x, bytes));
+  hipError_t e = hipMalloc(&y, bytes);
+  if (e != hipSuccess) {
+    (void)hipFree(x);
+    return hip_fail(e, "hipMalloc(autotune)");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  (void)hipMemsetAsync(x, 0x3f, bytes, s);
+  const int zcs[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
+  const TileShape shapes[] = {{64, 4, 0}, {64, 8, 0}, {32, 8, 0}};
+  TileShape best{64, 4, 16};
+  double best_t = 1e300;
+  fit_status st = FIT_OK;
+  for (TileShape base : shapes) {
+    for (int z : zcs) {
+      if (z > g->view.nz && z != zcs[0]) continue;
+      TileShape t = base;
+      t.zc = z;
+      double us = 0;
+      st = dtype == FIT_C128 ? time_shape<double>(g, t, scaling, omega, reps, x, y, s, &us)
+                             : time_shape<float>(g, t, scaling, omega, reps, x, y, s, &us);
+      if (st != FIT_OK) break;
+      if (us < best_t) {
+        best_t = us;
+        best = t;
+      }
+    }
+    if (st != FIT_OK) break;
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(x);
+  (void)hipFree(y);
+  if (st != FIT_OK) return st;
+  record_tile(g->view, dtype, best, best_t);
+  if (tx) *tx = best.tx;
+  if (ty) *ty = best.ty;
+  if (zc) *zc = best.zc;
+  if (best_us) *best_us = best_t;
+  return FIT_OK;
+}
+
+extern "C" fit_status fit_tune_save(const char* path) {
+  if (!path) {
+    set_error("fit_tune_save: NULL path");
+    return FIT_E_INVALID;
+  }
+  std::ostringstream os;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    os << "{\"arch\": \"gfx950\", \"entries\": [";
+    bool first = true;
+    for (auto& kv : g_tuned) {
+      int nx, ny, nz, dt;
+      std::tie(nx, ny, nz, dt) = kv.first;
+      os << (first ? "" : ", ") << "{\"nx\": " << nx << ", \"ny\": " << ny << ", \"nz\": " << nz
+         << ", \"dtype\": " << dt << ", \"tx\": " << kv.second.t.tx << ", \"ty\": " << kv.second.t.ty
+         << ", \"zc\": " << kv.second.t.zc << ", \"us\": " << kv.second.us << "}";
+      first = false;
+    }
+    os << "]}\n";
+  }
+  std::ofstream f(path);
+  if (!f) {
+    set_error(std::string("fit_tune_save: cannot open ") + path);
+    return FIT_E_INVALID;
+  }
+  f << os.str();
+  return FIT_OK;
+}
+
+// Minimal reader for the format written above: scans each {...} entry for its
+// integer/real fields.
+extern "C" fit_status fit_tune_load(const char* path) {
+  if (!path) {
+    set_error("fit_tune_load: NULL path");
+    return FIT_E_INVALID;
+  }
+  std::ifstream f(path);
+  if (!f) {
+    set_error(std::string("fit_tune_load: cannot open ") + path);
+    return FIT_E_INVALID;
+  }
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  size_t pos = s.find("\"entries\"");
+  if (pos == std::string::npos) {
+    set_error("fit_tune_load: no entries");
+    return FIT_E_INVALID;
+  }
+  auto field = [&](const std::string& obj, const char* key, double* v) -> bool {
+    std::string k = std::string("\"") + key + "\":";
+    size_t p = obj.find(k);
+    if (p == std::string::npos) return false;
+    *v = std::strtod(obj.c_str() + p + k.size(), nullptr);
+    return true;
+  };
+  int loaded = 0;
+  while ((pos = s.find('{', pos + 1)) != std::string::npos) {
+    size_t end = s.find('}', pos);
+    if (end == std::string::npos) break;
+    std::string obj = s.substr(pos, end - pos + 1);
+    double nx, ny, nz, dt, tx, ty, zc, us = 0;
+    if (field(obj, "nx", &nx) && field(obj, "ny", &ny) && field(obj, "nz", &nz) &&
+        field(obj, "dtype", &dt) && field(obj, "tx", &tx) && field(obj, "ty", &ty) &&
+        field(obj, "zc", &zc)) {
+      field(obj, "us", &us);
+      TileShape t{(int)tx, (int)ty, (int)zc};
+      if (tile_supported(t)) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[std::make_tuple((int)nx, (int)ny, (int)nz, (int)dt)] = TunedEntry{t, us};
+        ++loaded;
+      }
+    }
+    pos = end;
+  }
+  (void)loaded;
+  return FIT_OK;
+}

@@ -271,7 +271,7 @@ def layered_device(ncx: int, ncy: int, ncz: int, n_layers: int, n_strips: int,
         bc = (b0 + b1) // 2
         for end in (a0, a1):
             i, j = (end, bc) if axis == 0 else (bc, end)
-            if zc >= 1 and column_clear(i, j, zc):
+            if zc >= 1 and column_clear(i, j, zc) and all((q.i, q.j) != (i, j) for q in ports):
                 ports.append(Port(i=i, j=j, k0=0, k1=zc, z0=50.0))
                 break
 

@@ -1,0 +1,328 @@
+"""Thin ctypes binding of ``libfit.so`` (the C ABI declared in ``include/fit.h``).
+
+Only argument marshalling lives here: every step of the operator and the
+solvers runs in the library's HIP kernels.  PyTorch supplies device memory
+and streams (``tensor.data_ptr()``, ``torch.cuda.current_stream()``).  If the
+shared library is missing the binding raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+LIB_PATH = _HERE / "libfit.so"
+
+# status codes (fit_status)
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_NOT_CONVERGED, E_BREAKDOWN, E_NAN, E_UNSUPPORTED = range(8)
+STATUS_NAMES = ["FIT_OK", "FIT_E_INVALID", "FIT_E_NOMEM", "FIT_E_DEVICE", "FIT_E_NOT_CONVERGED",
+                "FIT_E_BREAKDOWN", "FIT_E_NAN", "FIT_E_UNSUPPORTED"]
+C128, C64 = 0, 1
+SCALE_NONE, SCALE_SYM = 0, 1
+BICGSTAB, GMRES, FGMRES = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+
+SOLVERS = {"bicgstab": BICGSTAB, "gmres": GMRES, "fgmres": FGMRES}
+SCALINGS = {"none": SCALE_NONE, "sym": SCALE_SYM}
+PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
+
+
+class FitError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 8 else status}: {msg}")
+        self.status = status
+
+
+class Material(C.Structure):
+    _fields_ = [("eps_r", C.c_double), ("mu_r", C.c_double), ("sigma", C.c_double),
+                ("tan_delta", C.c_double), ("is_pec", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Port(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("k0", C.c_int32), ("k1", C.c_int32),
+                ("z0", C.c_double)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("ncx", C.c_int32), ("ncy", C.c_int32), ("ncz", C.c_int32), ("nmat", C.c_int32),
+                ("dx", C.POINTER(C.c_double)), ("dy", C.POINTER(C.c_double)),
+                ("dz", C.POINTER(C.c_double)), ("cell_mat", C.POINTER(C.c_uint8)),
+                ("mats", C.POINTER(Material)), ("nports", C.c_int32),
+                ("pec_walls", C.c_uint32), ("ports", C.POINTER(Port))]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("solver", C.c_int32), ("restart", C.c_int32), ("max_iters", C.c_int32),
+                ("check_every", C.c_int32), ("precision", C.c_int32), ("scaling", C.c_int32),
+                ("inner_tol", C.c_double), ("precond", C.c_void_p), ("stream", C.c_void_p),
+                ("resid_history", C.POINTER(C.c_double)), ("resid_history_len", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("refinements", C.c_int32),
+                ("fell_back", C.c_int32), ("matvecs", C.c_int32), ("reserved", C.c_int32),
+                ("true_relres", C.c_double), ("time_ms", C.c_double),
+                ("bytes_moved", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class PrecondCfg(C.Structure):
+    _fields_ = [("base_channels", C.c_int32), ("steps", C.c_int32), ("batch", C.c_int32),
+                ("crop", C.c_int32), ("pairs_per_system", C.c_int32), ("seed", C.c_int32),
+                ("lr", C.c_double), ("weight_decay", C.c_double), ("stream", C.c_void_p)]
+
+
+# (name, restype, argtypes) of every exported entry point.
+_SIGS = [
+    ("fit_grid_create", C.c_int, [C.POINTER(GridDesc), C.c_int, C.POINTER(C.c_void_p)]),
+    ("fit_grid_destroy", None, [C.c_void_p]),
+    ("fit_num_edges", C.c_int64, [C.c_void_p]),
+    ("fit_edge_mask", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("fit_material_diag", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    ("fit_matvec", C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
+                             C.c_void_p]),
+    ("fit_matvec_batched", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_int,
+                                     C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("fit_solve", C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_double,
+                            C.POINTER(SolveOpts), C.c_void_p, C.POINTER(SolveInfo)]),
+    ("fit_sweep", C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_double), C.c_int,
+                            C.POINTER(C.c_void_p), C.c_int, C.c_double, C.POINTER(SolveOpts),
+                            C.POINTER(C.c_double), C.POINTER(C.c_void_p), C.POINTER(SolveInfo)]),
+    ("fit_port_voltages", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_double),
+                                    C.c_void_p]),
+    ("fit_precond_train", C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_double),
+                                    C.c_int, C.POINTER(PrecondCfg), C.POINTER(C.c_void_p)]),
+    ("fit_precond_create", C.c_int, [C.POINTER(PrecondCfg), C.c_int, C.POINTER(C.c_void_p)]),
+    ("fit_precond_save", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
+    ("fit_precond_load", C.c_int, [C.c_void_p, C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
+    ("fit_precond_apply", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
+    ("fit_precond_destroy", None, [C.c_void_p]),
+    ("fit_tile_set", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]),
+    ("fit_autotune", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p,
+                               C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double)]),
+    ("fit_tune_save", C.c_int, [C.c_char_p]),
+    ("fit_tune_load", C.c_int, [C.c_char_p]),
+    ("fit_last_error", C.c_char_p, []),
+    ("fit_version", C.c_char_p, []),
+]
+
+_lib = None
+
+
+def lib():
+    """Load ``libfit.so`` (built in-tree by ``paper_1705_08849_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1705_08849_amd.build` (no fallback exists)")
+        L = C.CDLL(str(LIB_PATH))
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return [s[0] for s in _SIGS]
+
+
+def last_error() -> str:
+    return lib().fit_last_error().decode()
+
+
+def check(status: int, what: str = ""):
+    if status != OK:
+        raise FitError(status, f"{what}: {last_error()}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+class Grid:
+    """A device-resident FIT grid (``fit_grid_create``).
+
+    ``dev`` is any object with ``dx, dy, dz`` (cell widths, m), ``cell_mat``
+    (uint8, shape ``(ncz, ncy, ncx)``), ``materials`` (objects with
+    ``eps_r, mu_r, sigma, tan_delta, is_pec``), ``ports`` (objects with
+    ``i, j, k0, k1, z0``) and ``pec_walls``.
+    """
+
+    def __init__(self, dev, device: int = 0):
+        L = lib()
+        self.dev = dev
+        self.device = device
+        self._keep = []
+        dx = np.ascontiguousarray(dev.dx, np.float64)
+        dy = np.ascontiguousarray(dev.dy, np.float64)
+        dz = np.ascontiguousarray(dev.dz, np.float64)
+        cm = np.ascontiguousarray(dev.cell_mat, np.uint8).ravel()
+        mats = (Material * len(dev.materials))(*[
+            Material(m.eps_r, m.mu_r, m.sigma, m.tan_delta, int(bool(m.is_pec)), 0)
+            for m in dev.materials])
+        nports = len(dev.ports)
+        ports = (Port * max(nports, 1))(*[Port(p.i, p.j, p.k0, p.k1, p.z0) for p in dev.ports])
+        self._keep = [dx, dy, dz, cm, mats, ports]
+        desc = GridDesc(len(dx), len(dy), len(dz), len(dev.materials),
+                        dx.ctypes.data_as(C.POINTER(C.c_double)),
+                        dy.ctypes.data_as(C.POINTER(C.c_double)),
+                        dz.ctypes.data_as(C.POINTER(C.c_double)),
+                        cm.ctypes.data_as(C.POINTER(C.c_uint8)), mats, nports,
+                        int(dev.pec_walls), ports)
+        h = C.c_void_p()
+        check(L.fit_grid_create(C.byref(desc), device, C.byref(h)), "fit_grid_create")
+        self.h = h
+        self.n_edges = int(L.fit_num_edges(h))
+        self.nodes = (len(dx) + 1, len(dy) + 1, len(dz) + 1)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fit_grid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- launch shapes --------------------------------------------------------
+    def set_tile(self, dtype: str, tx: int, ty: int, zc: int):
+        check(lib().fit_tile_set(self.h, {"c128": C128, "c64": C64}[dtype], tx, ty, zc),
+              "fit_tile_set")
+
+    def autotune(self, dtype: str = "c128", scaling: str = "none", omega: float = 2e10,
+                 reps: int = 10, stream=None):
+        tx, ty, zc, us = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        check(lib().fit_autotune(self.h, {"c128": C128, "c64": C64}[dtype], SCALINGS[scaling],
+                                 float(omega), reps, _stream_ptr(stream), C.byref(tx),
+                                 C.byref(ty), C.byref(zc), C.byref(us)), "fit_autotune")
+        return (tx.value, ty.value, zc.value), us.value
+
+    # -- debug exports ------------------------------------------------------
+    def edge_mask(self, stream=None):
+        torch = _torch()
+        m = torch.empty(self.n_edges, dtype=torch.uint8, device=f"cuda:{self.device}")
+        check(lib().fit_edge_mask(self.h, _dptr(m), _stream_ptr(stream)), "fit_edge_mask")
+        return m
+
+    def material_diag(self, kind: int, stream=None):
+        torch = _torch()
+        d = torch.empty(self.n_edges, dtype=torch.complex128, device=f"cuda:{self.device}")
+        check(lib().fit_material_diag(self.h, kind, _dptr(d), _stream_ptr(stream)),
+              "fit_material_diag")
+        return d
+
+    # -- operator -----------------------------------------------------------
+    def matvec(self, omega: float, x, y=None, scaling: str = "none", stream=None):
+        torch = _torch()
+        dt = {torch.complex128: C128, torch.complex64: C64}[x.dtype]
+        assert x.is_contiguous() and x.numel() == self.n_edges
+        if y is None:
+            y = torch.empty_like(x)
+        check(lib().fit_matvec(self.h, float(omega), dt, SCALINGS[scaling], _dptr(x), _dptr(y),
+                               _stream_ptr(stream)), "fit_matvec")
+        return y
+
+    def matvec_batched(self, omegas: Sequence[float], x, y=None, scaling: str = "none",
+                       stream=None):
+        torch = _torch()
+        dt = {torch.complex128: C128, torch.complex64: C64}[x.dtype]
+        nb = len(omegas)
+        assert x.is_contiguous() and x.numel() == nb * self.n_edges
+        if y is None:
+            y = torch.empty_like(x)
+        om = (C.c_double * nb)(*[float(o) for o in omegas])
+        check(lib().fit_matvec_batched(self.h, nb, om, dt, SCALINGS[scaling], _dptr(x), _dptr(y),
+                                       _stream_ptr(stream)), "fit_matvec_batched")
+        return y
+
+    # -- solve --------------------------------------------------------------
+    def solve(self, omega: float, source, tol: float = 1e-8, solver: str = "bicgstab",
+              restart: int = 30, max_iters: int = 0, check_every: int = 0,
+              precision: str = "fp64", scaling: str = "sym", inner_tol: float = 0.0,
+              precond=None, history: int = 0, use_graph: bool = False, x=None,
+              stream=None, raise_on_error: bool = True):
+        """Solve ``A(omega) e = -j omega j`` (``source`` = j, complex128 on the
+        device).  Returns ``(e, info_dict)``."""
+        torch = _torch()
+        assert source.dtype == torch.complex128 and source.numel() == self.n_edges
+        if x is None:
+            x = torch.empty_like(source)
+        hist = (C.c_double * history)() if history else None
+        opts = SolveOpts(SOLVERS[solver], restart, max_iters, check_every,
+                         PRECISIONS[precision], SCALINGS[scaling], inner_tol,
+                         C.c_void_p(precond.h.value if precond is not None else None),
+                         _stream_ptr(stream),
+                         C.cast(hist, C.POINTER(C.c_double)) if hist else None,
+                         history, int(bool(use_graph)))
+        info = SolveInfo()
+        st = lib().fit_solve(self.h, float(omega), _dptr(source), float(tol), C.byref(opts),
+                             _dptr(x), C.byref(info))
+        d = info.as_dict()
+        d["status_name"] = STATUS_NAMES[st] if 0 <= st < 8 else str(st)
+        if hist is not None:
+            d["history"] = np.array(hist[: min(history, max(info.iterations, 0))])
+        if st == E_INVALID or (raise_on_error and st not in (OK,)):
+            raise FitError(st, f"fit_solve: {last_error()} (info={d})")
+        return x, d
+
+    def port_voltages(self, x, nvec: int = 1, stream=None) -> np.ndarray:
+        n = len(self.dev.ports)
+        out = (C.c_double * (2 * max(1, n * nvec)))()
+        check(lib().fit_port_voltages(self.h, _dptr(x), nvec, out, _stream_ptr(stream)),
+              "fit_port_voltages")
+        a = np.frombuffer(out, dtype=np.float64)[: 2 * n * nvec].copy()
+        return a.view(np.complex128).reshape(nvec, n)
+
+
+def sweep(grids: Sequence[Grid], omegas: Sequence[float], sources, tol: float = 1e-8,
+          solver: str = "bicgstab", precision: str = "mixed", scaling: str = "sym",
+          max_iters: int = 0, check_every: int = 0, inner_tol: float = 0.0, xs=None,
+          restart: int = 30, stream=None):
+    """``fit_sweep``: solve every (grid, omega, rhs) system.  ``sources[g]`` is
+    a complex128 tensor of shape ``(nrhs, n_e(g))``.  Returns
+    ``(status, port_voltages list per grid [nomega, nrhs, nports], infos)``."""
+    ng, nf = len(grids), len(omegas)
+    nrhs = int(sources[0].shape[0])
+    gh = (C.c_void_p * ng)(*[g.h.value for g in grids])
+    om = (C.c_double * nf)(*[float(o) for o in omegas])
+    src = (C.c_void_p * ng)(*[s.data_ptr() for s in sources])
+    npts = [len(g.dev.ports) for g in grids]
+    tot = sum(nf * nrhs * p for p in npts)
+    pv = (C.c_double * (2 * max(tot, 1)))()
+    xp = (C.c_void_p * ng)(*[x.data_ptr() for x in xs]) if xs is not None else None
+    infos = (SolveInfo * (ng * nf * nrhs))()
+    opts = SolveOpts(SOLVERS[solver], restart, max_iters, check_every, PRECISIONS[precision],
+                     SCALINGS[scaling], inner_tol, None, _stream_ptr(stream), None, 0, 1)
+    st = lib().fit_sweep(gh, ng, om, nf, src, nrhs, float(tol), C.byref(opts), pv, xp, infos)
+    if st == E_INVALID:
+        raise FitError(st, f"fit_sweep: {last_error()}")
+    a = np.frombuffer(pv, dtype=np.float64)[: 2 * tot].copy().view(np.complex128)
+    out, off = [], 0
+    for p in npts:
+        out.append(a[off: off + nf * nrhs * p].reshape(nf, nrhs, p))
+        off += nf * nrhs * p
+    return st, out, [infos[q].as_dict() for q in range(ng * nf * nrhs)]

@@ -1,0 +1,95 @@
+"""The C ABI library loads and exports every entry point declared in
+include/fit.h; host-side argument validation needs no GPU."""
+import ctypes as C
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from paper_1705_08849_amd import fit
+from paper_1705_08849_amd import devices as D
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def declared_functions():
+    text = (ROOT / "include" / "fit.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fit_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fit.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(fit.exported_symbols())
+
+
+def test_version_and_error_string():
+    assert fit.lib().fit_version().decode().startswith("fit-mi355x")
+    assert isinstance(fit.last_error(), str)
+
+
+def _desc(dev, **over):
+    dx = np.ascontiguousarray(dev.dx)
+    dy = np.ascontiguousarray(dev.dy)
+    dz = np.ascontiguousarray(dev.dz)
+    cm = np.ascontiguousarray(dev.cell_mat).ravel()
+    mats = (fit.Material * len(dev.materials))(*[
+        fit.Material(m.eps_r, m.mu_r, m.sigma, m.tan_delta, int(m.is_pec), 0)
+        for m in dev.materials])
+    ports = (fit.Port * max(1, len(dev.ports)))(*[fit.Port(p.i, p.j, p.k0, p.k1, p.z0)
+                                                   for p in dev.ports])
+    d = fit.GridDesc(len(dx), len(dy), len(dz), len(dev.materials),
+                     dx.ctypes.data_as(C.POINTER(C.c_double)),
+                     dy.ctypes.data_as(C.POINTER(C.c_double)),
+                     dz.ctypes.data_as(C.POINTER(C.c_double)),
+                     cm.ctypes.data_as(C.POINTER(C.c_uint8)), mats, len(dev.ports),
+                     dev.pec_walls, ports)
+    for k, v in over.items():
+        setattr(d, k, v)
+    return d, (dx, dy, dz, cm, mats, ports)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ncx=0), dict(nmat=0), dict(nmat=255), dict(pec_walls=0x40), dict(nports=65),
+])
+def test_grid_create_rejects_invalid_descriptors(bad):
+    dev = D.layered_device(6, 5, 4, n_layers=2, n_strips=1, n_ports=1, seed=1)
+    d, keep = _desc(dev, **bad)
+    h = C.c_void_p()
+    st = fit.lib().fit_grid_create(C.byref(d), 0, C.byref(h))
+    assert st == fit.E_INVALID and not h.value
+    assert fit.last_error()
+
+
+def test_grid_create_rejects_bad_geometry_and_ports():
+    dev = D.cavity(4, 4, 4)
+    dev.dx[1] = -1.0
+    d, keep = _desc(dev)
+    h = C.c_void_p()
+    assert fit.lib().fit_grid_create(C.byref(d), 0, C.byref(h)) == fit.E_INVALID
+    dev = D.cavity(4, 4, 4)
+    dev.cell_mat[1, 1, 1] = 3
+    d, keep = _desc(dev)
+    assert fit.lib().fit_grid_create(C.byref(d), 0, C.byref(h)) == fit.E_INVALID
+    dev = D.cavity(4, 4, 4)
+    dev.ports = [D.Port(1, 1, 0, 2), D.Port(1, 1, 2, 4)]  # two ports on one column
+    d, keep = _desc(dev)
+    assert fit.lib().fit_grid_create(C.byref(d), 0, C.byref(h)) == fit.E_INVALID
+    assert "column" in fit.last_error()
+    dev.ports = [D.Port(1, 1, 2, 6)]  # beyond ncz
+    d, keep = _desc(dev)
+    assert fit.lib().fit_grid_create(C.byref(d), 0, C.byref(h)) == fit.E_INVALID
+
+
+def test_null_arguments_are_rejected():
+    L = fit.lib()
+    assert L.fit_matvec(None, 1.0, 0, 0, None, None, None) == fit.E_INVALID
+    assert L.fit_edge_mask(None, None, None) == fit.E_INVALID
+    assert L.fit_num_edges(None) == -1
+    L.fit_grid_destroy(None)
+    assert L.fit_tile_set(None, 0, 64, 4, 8) == fit.E_INVALID
