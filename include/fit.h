@@ -66,7 +66,11 @@ typedef enum { FIT_C128 = 0, FIT_C64 = 1 } fit_dtype;
  *   eqs. (e2s)/(e2t), S C^T M_nu C S - omega^2 I.  Requires omega > 0. */
 typedef enum { FIT_SCALE_NONE = 0, FIT_SCALE_SYM = 1 } fit_scaling;
 
-typedef enum { FIT_BICGSTAB = 0, FIT_GMRES = 1, FIT_FGMRES = 2 } fit_solver;
+/* FIT_COCG is the paper's conjugate-gradient method (Sec. IV, "cg") in the
+ * form that is valid for the complex symmetric (A = A^T, not Hermitian)
+ * operator: CG recurrences with the unconjugated bilinear form x^T y
+ * (conjugate orthogonal CG).  One operator application per iteration. */
+typedef enum { FIT_BICGSTAB = 0, FIT_GMRES = 1, FIT_FGMRES = 2, FIT_COCG = 3 } fit_solver;
 
 /* FIT_PREC_FP64:  complex128 operator and Krylov vectors throughout.
  * FIT_PREC_MIXED: complex64 operator and inner Krylov iterations, complex128

@@ -309,11 +309,35 @@ def relative_residual(dev, omega: float, jsrc: np.ndarray, x: np.ndarray) -> flo
 # Textbook Krylov methods (the paper's KSP choices, Sec. IV), plain NumPy.
 # ---------------------------------------------------------------------------
 
-def bicgstab(a, b, tol=1e-8, maxiter=100000, x0=None):
-    """Complex BiCGStab (van der Vorst, 1992) with ``r_hat = r_0`` and
-    conjugated inner products; stops when the recursively updated residual
-    satisfies ``||r|| <= tol ||b||`` and the true residual agrees, restarting
-    from the current iterate otherwise.  Returns ``(x, iterations, relres)``."""
+SPLITMIX_GAMMA = 0x9E3779B97F4A7C15
+
+
+def splitmix64(counter: np.ndarray, seed: int) -> np.ndarray:
+    """SplitMix64 (Steele, Lea & Flood 2014) evaluated at ``seed + (counter+1)
+    * gamma``: a counter-based generator, one 64-bit output per counter."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (counter.astype(np.uint64) + np.uint64(1)) * np.uint64(SPLITMIX_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def shadow_vector(n_edges: int, seed: int = 0x5EED) -> np.ndarray:
+    """Dense pseudo-random BiCGStab shadow vector over all edge indices:
+    re, im uniform in [-1, 1) from counters 2e and 2e+1 (top 53 bits)."""
+    e = np.arange(n_edges, dtype=np.uint64)
+    u = (splitmix64(2 * e, seed) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    v = (splitmix64(2 * e + np.uint64(1), seed) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return (2.0 * u - 1.0) + 1j * (2.0 * v - 1.0)
+
+
+def bicgstab(a, b, tol=1e-8, maxiter=100000, x0=None, rhat=None):
+    """Complex BiCGStab (van der Vorst, 1992) with conjugated inner products;
+    the shadow vector is ``r_hat = r_0`` unless ``rhat`` is given (any vector
+    with <r_hat, r_0> != 0 is admissible).  Stops when the recursively
+    updated residual satisfies ``||r|| <= tol ||b||`` and the true residual
+    agrees, restarting from the current iterate otherwise.  Returns
+    ``(x, iterations, relres)``."""
     nb = np.linalg.norm(b)
     x = np.zeros_like(b) if x0 is None else x0.astype(np.complex128).copy()
     it = 0
@@ -321,7 +345,7 @@ def bicgstab(a, b, tol=1e-8, maxiter=100000, x0=None):
         r = b - a @ x
         if np.linalg.norm(r) <= tol * nb:
             break
-        rh = r.copy()
+        rh = r.copy() if rhat is None else np.asarray(rhat, np.complex128).copy()
         rho_old = alpha = omg = 1.0 + 0j
         v = np.zeros_like(b)
         p = np.zeros_like(b)
@@ -346,6 +370,38 @@ def bicgstab(a, b, tol=1e-8, maxiter=100000, x0=None):
         if np.linalg.norm(b - a @ x) <= tol * nb:
             break
     return x, it, float(np.linalg.norm(b - a @ x) / nb)
+
+
+def cocg(a, b, tol=1e-8, maxiter=100000, x0=None, history=False):
+    """Conjugate orthogonal conjugate gradients (van der Vorst & Melissen,
+    1990): the CG recurrences with the unconjugated bilinear form x^T y,
+    valid for complex symmetric A.  Stops when ``||r|| <= tol ||b||``
+    (recursive residual, checked against the true one at the end).
+    Returns ``(x, iterations, relres)`` and, with ``history``, the
+    recursive relative residual after every iteration."""
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b) if x0 is None else x0.astype(np.complex128).copy()
+    r = b - a @ x
+    p = np.zeros_like(b)
+    rho = r @ r
+    beta = 0.0
+    hist = []
+    it = 0
+    while it < maxiter and np.linalg.norm(r) > tol * nb:
+        it += 1
+        p = r + beta * p
+        q = a @ p
+        alpha = rho / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        rho_new = r @ r
+        beta = rho_new / rho
+        rho = rho_new
+        hist.append(np.linalg.norm(r) / nb)
+    rr = float(np.linalg.norm(b - a @ x) / nb)
+    if history:
+        return x, it, rr, np.array(hist)
+    return x, it, rr
 
 
 def gmres(a, b, restart=30, tol=1e-8, maxiter=100000, precond=None, x0=None):

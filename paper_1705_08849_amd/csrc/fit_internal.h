@@ -115,6 +115,19 @@ __host__ __device__ __forceinline__ cx<T> cdotc(cx<T> a, cx<T> b) {
 template <class T>
 __host__ __device__ __forceinline__ T cabs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
 
+// Products feeding reductions are formed in double: complex64 iterates can
+// exceed the float range once squared (the scaled operator carries omega^2).
+template <class T>
+__host__ __device__ __forceinline__ cx<double> cdotc_d(cx<T> a, cx<T> b) {
+  const double ar = a.re, ai = a.im, br = b.re, bi = b.im;
+  return {ar * br + ai * bi, ar * bi - ai * br};
+}
+template <class T>
+__host__ __device__ __forceinline__ double cabs2_d(cx<T> a) {
+  const double r = a.re, i = a.im;
+  return r * r + i * i;
+}
+
 // 1/sqrt(z), principal branch (Re sqrt(z) >= 0).
 // Uses t = sqrt((|z| + |Re z|)/2), which involves no cancellation; the other
 // component follows from Im z = 2 u v.  Undefined for z = 0.
@@ -310,6 +323,7 @@ struct fit_grid {
   // per-grid workspace arena (grown on demand; freed by destroy)
   fit::Workspace ws;
   fit::Workspace red;  // reduction partials + counters + solver state
+  void* pinned = nullptr;  // pinned host mirror of the solver state
 };
 
 namespace fit {

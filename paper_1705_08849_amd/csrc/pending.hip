@@ -1,6 +1,7 @@
 // Entry points declared in fit.h whose implementation has not landed yet.
 // Each reports FIT_E_UNSUPPORTED with a message.
 #include "fit_internal.h"
+#include "precond.h"
 
 using namespace fit;
 
@@ -13,17 +14,10 @@ extern "C" fit_status fit_matvec_batched(const fit_grid*, int, const double*, in
                                          void*, void*) {
   return unsupported("fit_matvec_batched");
 }
-extern "C" fit_status fit_solve(fit_grid*, double, const void*, double, const fit_solve_opts*, void*,
-                                fit_solve_info*) {
-  return unsupported("fit_solve");
-}
 extern "C" fit_status fit_sweep(fit_grid* const*, int, const double*, int, const void* const*, int,
                                 double, const fit_solve_opts*, double*, void* const*,
                                 fit_solve_info*) {
   return unsupported("fit_sweep");
-}
-extern "C" fit_status fit_port_voltages(const fit_grid*, const void*, int, double*, void*) {
-  return unsupported("fit_port_voltages");
 }
 extern "C" fit_status fit_precond_train(fit_grid* const*, int, const double*, int,
                                         const fit_precond_cfg*, fit_precond**) {
@@ -43,3 +37,7 @@ extern "C" fit_status fit_precond_apply(fit_precond*, const fit_grid*, double, c
   return unsupported("fit_precond_apply");
 }
 extern "C" void fit_precond_destroy(fit_precond*) {}
+
+namespace fit {
+PrecondApply* precond_apply_of(fit_precond*, const fit_grid*, double) { return nullptr; }
+}  // namespace fit

@@ -1,0 +1,1389 @@
+// fit_solve: BiCGStab, restarted GMRES(m) and flexible GMRES(m) around the
+// matrix-free operator, in complex128 or in complex64 with complex128
+// iterative refinement.  The iteration always stops on the true relative
+// residual of the unscaled complex128 system.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "fit_internal.h"
+#include "krylov.h"
+#include "precond.h"
+#include "stencil.h"
+#include "tuning.h"
+
+namespace fit {
+
+// ---------------------------------------------------------------------------
+// Node-wise transforms that need the per-edge coefficients (mask, scaling).
+// ---------------------------------------------------------------------------
+enum XformKind { XF_RHS = 0, XF_SCALE = 1, XF_AXPY = 2, XF_SHADOW = 3 };
+
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator: the
+// output for counter c is the mix of seed + (c+1) * gamma.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t counter, uint64_t seed) {
+  uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kShadowSeed = 0x5EED;
+
+// Uniform [-1, 1) from the top 53 bits.
+__device__ __forceinline__ double u11(uint64_t h) {
+  return 2.0 * ((double)(h >> 11) * 0x1.0p-53) - 1.0;
+}
+
+template <class TI, class TO, int KIND>
+__global__ void __launch_bounds__(256)
+    node_xform_kernel(GridView g, double omega, int sym, int inverse, const TI* in, TO* out,
+                      double factor, RedOut* red, double* part, unsigned* cnt) {
+  __shared__ MatLds<double> mat;
+  __shared__ double lds[4];
+  fill_mat_mode<double>(mat, g.mats, omega, MODE_MEC);
+  __syncthreads();
+  double acc[1] = {0.0};
+  int bad = 0;
+  const cx<double> pc = port_coef_mode<double>(omega, MODE_MEC);
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.np;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % g.nx);
+    const int j = (int)((n / g.nx) % g.ny);
+    const int p = (int)(n / ((int64_t)g.nx * g.ny));
+    const ColGeo<double> cg = col_geo<double>(g, i, j);
+    const PlaneRec<double> lo = plane_rec(mat, cg, load_cell_ids(g, i, j, p - 1));
+    const PlaneRec<double> hi = plane_rec(mat, cg, load_cell_ids(g, i, j, p));
+    const ZGeo<double> z = zgeo<double>(g, p);
+    const NodeCoef<double> nc = node_coef(cg, lo, hi, z.hzl, z.hzh, z.ivz, p, pc);
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const int64_t e = 3 * n + w;
+      const bool fr = (nc.mask >> w) & 1u;
+      const cx<TI> vi = ldc(in, e);
+      const cx<double> v{(double)vi.re, (double)vi.im};
+      if (KIND == XF_SHADOW) {
+        // dense pseudo-random BiCGStab shadow vector on the free edges
+        const double re = u11(splitmix64(2ull * (uint64_t)e, kShadowSeed));
+        const double im = u11(splitmix64(2ull * (uint64_t)e + 1ull, kShadowSeed));
+        const cx<double> sv = fr ? cx<double>{re, im} : cx<double>{0.0, 0.0};
+        stc(out, e, cx<TO>{(TO)sv.re, (TO)sv.im});
+        acc[0] += cabs2(sv);
+        (void)v;
+      } else if (KIND == XF_RHS) {
+        // b = -j omega j
+        const cx<double> b = fr ? cx<double>{omega * v.im, -omega * v.re} : cx<double>{0.0, 0.0};
+        if (!fr && (v.re != 0.0 || v.im != 0.0)) bad = 1;
+        stc(out, e, cx<TO>{(TO)b.re, (TO)b.im});
+        acc[0] += cabs2(b);
+      } else {
+        cx<double> s{1.0, 0.0};
+        if (sym && fr) {
+          s = crsqrt(nc.e[w]);
+          if (inverse) {
+            const double a2 = cabs2(s);
+            s = cx<double>{s.re / a2, -s.im / a2};
+          }
+        }
+        cx<double> r = fr ? factor * (s * v) : cx<double>{0.0, 0.0};
+        if (KIND == XF_AXPY) {
+          const cx<TO> o = ldc(out, e);
+          r = cx<double>{r.re + (double)o.re, r.im + (double)o.im};
+          if (!fr) r = cx<double>{0.0, 0.0};
+        }
+        stc(out, e, cx<TO>{(TO)r.re, (TO)r.im});
+        acc[0] += cabs2(r);
+      }
+    }
+  }
+  if (red) {
+    if (bad) atomicOr(&red->flag, 1);
+    double outv[1];
+    if (grid_reduce<1>(acc, part, cnt, lds, outv)) {
+      if (threadIdx.x == 0) red->v[0] = outv[0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Element-wise vector kernels.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) zero_kernel(T* v, int64_t n2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2;
+       e += (int64_t)gridDim.x * blockDim.x)
+    v[e] = T(0);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) copy_kernel(const T* a, T* b, int64_t n2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2;
+       e += (int64_t)gridDim.x * blockDim.x)
+    b[e] = a[e];
+}
+
+// BiCGStab step 3: x += alpha p + omega s, r = s - omega t, <r_hat, r>, ||r||^2,
+// then the next beta and the termination tests.
+template <class T>
+__global__ void __launch_bounds__(256)
+    bicg_update_kernel(T* x, T* r, const T* p, const T* s, const T* t, const T* rh, int64_t n,
+                       BiState* st, double* part, unsigned* cnt) {
+  __shared__ double lds[3 * 4];
+  if (*(volatile int*)&st->done != kRunning) return;
+  const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
+  const cx<T> om{(T)st->omega.re, (T)st->omega.im};
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> sv = ldc(s, e);
+    const cx<T> xv = ldc(x, e) + al * ldc(p, e) + om * sv;
+    const cx<T> rv = sv - om * ldc(t, e);
+    stc(x, e, xv);
+    stc(r, e, rv);
+    const cx<double> d = cdotc_d(ldc(rh, e), rv);
+    acc[0] += d.re;
+    acc[1] += d.im;
+    acc[2] += cabs2_d(rv);
+  }
+  double sum[3];
+  if (grid_reduce<3>(acc, part, cnt, lds, sum) && threadIdx.x == 0) {
+    const cx<double> rho_new{sum[0], sum[1]};
+    const double rr = sum[2];
+    st->iter += 1;
+    if (st->hist && st->iter <= st->hist_len) st->hist[st->iter - 1] = sqrt(rr) * st->hscale;
+    if (!isfinite(rr) || !isfinite(sum[0]) || !isfinite(sum[1])) {
+      st->done = kNan;
+      return;
+    }
+    // beta = (rho_new / rho) * (alpha / omega)
+    const cx<double> rho = st->rho, a = st->alpha, w = st->omega;
+    const double r2 = cabs2(rho), w2 = cabs2(w);
+    st->rr = rr;
+    if (rr <= st->tol2) {
+      st->done = kConverged;
+      st->rho = rho_new;
+      return;
+    }
+    // <r_hat, r> negligible against |r_hat| |r| at the working precision:
+    // the shadow space has collapsed (restart)
+    if (r2 == 0.0 || w2 == 0.0 || cabs2(rho_new) < 1e-28 * rr * st->rhrh) {
+      st->reason = (r2 == 0.0 || w2 == 0.0) ? 4 : 3;
+      st->done = kBreakdown;
+      return;
+    }
+    const cx<double> q{(rho_new.re * rho.re + rho_new.im * rho.im) / r2,
+                       (rho_new.im * rho.re - rho_new.re * rho.im) / r2};
+    const cx<double> aw{(a.re * w.re + a.im * w.im) / w2, (a.im * w.re - a.re * w.im) / w2};
+    st->beta = q * aw;
+    st->rho = rho_new;
+    if (st->iter >= st->max_iter) st->done = kMaxIter;
+  }
+}
+
+// Multi-dot h_i = <V_i, w>, i < nv: each block keeps its chunk of w in
+// registers and walks the basis vectors; partials[i * nblk + blk].
+constexpr int kMdPer = 4;  // complex elements per thread
+template <class T>
+__global__ void __launch_bounds__(256)
+    multidot_kernel(const T* V, int64_t ldv, int nv, const T* w, int64_t n, double* part,
+                    const GmState* st) {
+  __shared__ double lds[2 * 4];
+  if (st && *(volatile const int*)&st->done != kRunning) return;
+  const int64_t base = (int64_t)blockIdx.x * 256 * kMdPer;
+  cx<T> wl[kMdPer];
+#pragma unroll
+  for (int q = 0; q < kMdPer; ++q) {
+    const int64_t e = base + q * 256 + threadIdx.x;
+    wl[q] = e < n ? ldc(w, e) : cx<T>{T(0), T(0)};
+  }
+  for (int i = 0; i < nv; ++i) {
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < kMdPer; ++q) {
+      const int64_t e = base + q * 256 + threadIdx.x;
+      if (e < n) {
+        const cx<double> d = cdotc_d(ldc(V + 2 * ldv * i, e), wl[q]);
+        acc[0] += d.re;
+        acc[1] += d.im;
+      }
+    }
+    block_reduce<2>(acc, lds);
+    if (threadIdx.x == 0) {
+      part[2 * ((int64_t)i * gridDim.x + blockIdx.x)] = acc[0];
+      part[2 * ((int64_t)i * gridDim.x + blockIdx.x) + 1] = acc[1];
+    }
+  }
+}
+
+// Sum the multi-dot partials: one block per basis vector, fixed order.
+__global__ void __launch_bounds__(256)
+    multidot_finish_kernel(const double* part, int nblk, GmState* st, int accumulate) {
+  __shared__ double lds[2 * 4];
+  if (*(volatile int*)&st->done != kRunning) return;
+  const int i = blockIdx.x;
+  double acc[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    acc[0] += part[2 * ((int64_t)i * nblk + b)];
+    acc[1] += part[2 * ((int64_t)i * nblk + b) + 1];
+  }
+  block_reduce<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    st->hcol[i] = cx<double>{acc[0], acc[1]};
+    const int ld = st->m + 1;
+    cx<double>& h = st->h[(int64_t)st->j * ld + i];
+    h = accumulate ? h + st->hcol[i] : st->hcol[i];
+  }
+}
+
+// w -= sum_i hcol_i V_i; optionally ||w||^2 into `out`.
+template <class T>
+__global__ void __launch_bounds__(256)
+    multi_axpy_kernel(const T* V, int64_t ldv, int nv, T* w, int64_t n, GmState* st,
+                      RedOut* out, double* part, unsigned* cnt) {
+  __shared__ double lds[4];
+  __shared__ cx<double> hc[kMaxRestart + 1];
+  if (*(volatile int*)&st->done != kRunning) return;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) hc[i] = st->hcol[i];
+  __syncthreads();
+  double acc[1] = {0.0};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    cx<T> v = ldc(w, e);
+    for (int i = 0; i < nv; ++i) {
+      const cx<T> h{(T)hc[i].re, (T)hc[i].im};
+      v = v - h * ldc(V + 2 * ldv * i, e);
+    }
+    stc(w, e, v);
+    acc[0] += cabs2_d(v);
+  }
+  if (out) {
+    double s[1];
+    if (grid_reduce<1>(acc, part, cnt, lds, s) && threadIdx.x == 0) out->v[0] = s[0];
+  }
+}
+
+// Completes Arnoldi step j: h_{j+1,j} = ||w||, applies the previous Givens
+// rotations to column j, forms the new one, updates g and tests convergence.
+__global__ void gmres_step_kernel(GmState* st, const RedOut* wn) {
+  if (threadIdx.x != 0 || st->done != kRunning) return;
+  const int m = st->m, ld = m + 1, j = st->j;
+  cx<double>* h = st->h + (int64_t)j * ld;
+  const double hn = sqrt(wn->v[0]);
+  h[j + 1] = cx<double>{hn, 0.0};
+  for (int i = 0; i < j; ++i) {
+    const cx<double> c = st->cs[i], s = st->sn[i];
+    const cx<double> a = h[i], b = h[i + 1];
+    // [conj(c) conj(s); -s c] applied to (a, b)
+    h[i] = cx<double>{c.re * a.re + c.im * a.im + s.re * b.re + s.im * b.im,
+                      c.re * a.im - c.im * a.re + s.re * b.im - s.im * b.re};
+    h[i + 1] = cx<double>{-(s.re * a.re - s.im * a.im) + (c.re * b.re - c.im * b.im),
+                          -(s.re * a.im + s.im * a.re) + (c.re * b.im + c.im * b.re)};
+  }
+  const cx<double> a = h[j], b = h[j + 1];
+  const double rho = sqrt(cabs2(a) + cabs2(b));
+  cx<double> c{1.0, 0.0}, s{0.0, 0.0};
+  if (rho > 0.0) {
+    c = cx<double>{a.re / rho, a.im / rho};
+    s = cx<double>{b.re / rho, b.im / rho};
+  }
+  st->cs[j] = c;
+  st->sn[j] = s;
+  h[j] = cx<double>{rho, 0.0};
+  h[j + 1] = cx<double>{0.0, 0.0};
+  const cx<double> gj = st->g[j];
+  st->g[j + 1] = cx<double>{-(s.re * gj.re - s.im * gj.im), -(s.re * gj.im + s.im * gj.re)};
+  st->g[j] = cx<double>{c.re * gj.re + c.im * gj.im, c.re * gj.im - c.im * gj.re};
+  st->iter += 1;
+  const double res = sqrt(cabs2(st->g[j + 1]));
+  if (st->hist && st->iter <= st->hist_len) st->hist[st->iter - 1] = res * st->hscale;
+  st->k = j + 1;
+  st->vscale = hn > 0.0 ? 1.0 / hn : 0.0;
+  st->j = j + 1;
+  if (!isfinite(res) || !isfinite(hn)) {
+    st->done = kNan;
+  } else if (res <= st->tol) {
+    st->done = kConverged;
+  } else if (hn == 0.0) {
+    st->done = kConverged;  // lucky breakdown: the Krylov space is invariant
+  } else if (st->iter >= st->max_iter) {
+    st->done = kMaxIter;
+  } else if (st->j >= m) {
+    st->done = kBreakdown;  // cycle complete: restart (not a failure)
+  }
+}
+
+// Back substitution of the k x k upper-triangular least-squares system.
+__global__ void gmres_solve_kernel(GmState* st) {
+  if (threadIdx.x != 0) return;
+  const int k = st->k, ld = st->m + 1;
+  for (int i = k - 1; i >= 0; --i) {
+    cx<double> v = st->g[i];
+    for (int q = i + 1; q < k; ++q) v = v - st->h[(int64_t)q * ld + i] * st->y[q];
+    const cx<double> d = st->h[(int64_t)i * ld + i];
+    const double d2 = cabs2(d);
+    st->y[i] = d2 > 0 ? cx<double>{(v.re * d.re + v.im * d.im) / d2, (v.im * d.re - v.re * d.im) / d2}
+                      : cx<double>{0.0, 0.0};
+  }
+}
+
+// x += sum_i y_i B_i (B = V for GMRES, Z for FGMRES).
+template <class T>
+__global__ void __launch_bounds__(256)
+    gmres_update_kernel(T* x, const T* B, int64_t ldb, int64_t n, const GmState* st) {
+  __shared__ cx<double> yl[kMaxRestart];
+  const int k = st->k;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) yl[i] = st->y[i];
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    cx<T> v = ldc(x, e);
+    for (int i = 0; i < k; ++i) v = v + cx<T>{(T)yl[i].re, (T)yl[i].im} * ldc(B + 2 * ldb * i, e);
+    stc(x, e, v);
+  }
+}
+
+// COCG step 2: x += alpha p, r -= alpha q, r^T r, ||r||^2, next beta and the
+// termination tests.
+template <class T>
+__global__ void __launch_bounds__(256)
+    cocg_update_kernel(T* x, T* r, const T* p, const T* q, int64_t n, CgState* st, double* part,
+                       unsigned* cnt) {
+  __shared__ double lds[3 * 4];
+  if (*(volatile int*)&st->done != kRunning) return;
+  const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> xv = ldc(x, e) + al * ldc(p, e);
+    const cx<T> rv = ldc(r, e) - al * ldc(q, e);
+    stc(x, e, xv);
+    stc(r, e, rv);
+    const double rr = rv.re, ri = rv.im;
+    acc[0] += rr * rr - ri * ri;
+    acc[1] += 2.0 * rr * ri;
+    acc[2] += rr * rr + ri * ri;
+  }
+  double sum[3];
+  if (grid_reduce<3>(acc, part, cnt, lds, sum) && threadIdx.x == 0) {
+    const cx<double> rho_new{sum[0], sum[1]};
+    const double rr = sum[2];
+    st->iter += 1;
+    if (st->hist && st->iter <= st->hist_len) st->hist[st->iter - 1] = sqrt(rr) * st->hscale;
+    if (!isfinite(rr) || !isfinite(sum[0]) || !isfinite(sum[1])) {
+      st->done = kNan;
+      return;
+    }
+    st->rr = rr;
+    if (rr <= st->tol2) {
+      st->done = kConverged;
+      return;
+    }
+    const cx<double> rho = st->rho;
+    const double r2 = cabs2(rho);
+    if (r2 == 0.0 || cabs2(rho_new) < 1e-28 * rr * rr) {
+      st->reason = 3;  // r^T r vanishes: r is (nearly) a quasi-null vector
+      st->done = kBreakdown;
+      return;
+    }
+    st->beta = cx<double>{(rho_new.re * rho.re + rho_new.im * rho.im) / r2,
+                          (rho_new.im * rho.re - rho_new.re * rho.im) / r2};
+    st->rho = rho_new;
+    if (st->iter >= st->max_iter) st->done = kMaxIter;
+  }
+}
+
+// <a, b> (or the bilinear a^T b), ||a||^2, ||b||^2 -> out->v[0..3].
+template <class T, bool BILINEAR = false>
+__global__ void __launch_bounds__(256)
+    dot_kernel(const T* a, const T* b, int64_t n, RedOut* out, double* part, unsigned* cnt) {
+  __shared__ double lds[4 * 4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> av = ldc(a, e), bv = ldc(b, e);
+    const cx<double> d = BILINEAR ? cdotc_d(cx<T>{av.re, -av.im}, bv) : cdotc_d(av, bv);
+    acc[0] += d.re;
+    acc[1] += d.im;
+    acc[2] += cabs2_d(av);
+    acc[3] += cabs2_d(bv);
+  }
+  double s[4];
+  if (grid_reduce<4>(acc, part, cnt, lds, s) && threadIdx.x == 0) {
+    for (int q = 0; q < 4; ++q) out->v[q] = s[q];
+  }
+}
+
+// v_j = w * vscale (FGMRES keeps the normalised vector for the preconditioner).
+template <class T>
+__global__ void __launch_bounds__(256)
+    gm_normalize_kernel(const T* w, T* v, int64_t n, const GmState* st) {
+  if (*(volatile const int*)&st->done != kRunning) return;
+  const T sc = (T)st->vscale;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    stc(v, e, sc * ldc(w, e));
+}
+
+// Re-arm the state after a completed cycle so the restart's operator
+// application runs.
+__global__ void gm_restart_prep_kernel(GmState* st) {
+  if (threadIdx.x == 0) st->done = kRunning;
+}
+
+// w = r0 - w, ||w||^2.
+template <class T>
+__global__ void __launch_bounds__(256)
+    sub_norm_kernel(const T* r0, T* w, int64_t n, RedOut* out, double* part, unsigned* cnt) {
+  __shared__ double lds[4];
+  double acc[1] = {0.0};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> v = ldc(r0, e) - ldc(w, e);
+    stc(w, e, v);
+    acc[0] += cabs2_d(v);
+  }
+  double s[1];
+  if (grid_reduce<1>(acc, part, cnt, lds, s) && threadIdx.x == 0) out->v[0] = s[0];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side solver context.
+// ---------------------------------------------------------------------------
+struct Ctx {
+  fit_grid* g;
+  hipStream_t s;
+  double omega;
+  int sym;
+  // reduction scratch
+  double* part;
+  unsigned* cnt;
+  RedOut* red;
+  BiState* bst;
+  GmState* gst;
+  RedOut* h_red;   // pinned host mirrors
+  BiState* h_bst;
+  GmState* h_gst;
+  CgState* cst = nullptr;
+  CgState* h_cst = nullptr;
+  int max_blocks;
+  double bytes = 0.0;  // algorithmic bytes launched
+  int matvecs = 0;
+  int last_reason = 0;   // breakdown test of the last inner BiCGStab
+  double last_rr = 0.0;  // its final recursive ||r||^2 (unit initial norm)
+  TileShape tile128, tile64;
+};
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+template <class T, class Op>
+static fit_status launch_op_stencil_mode(Ctx& c, bool sym, const Op& op) {
+  const TileShape t = sizeof(T) == 8 ? c.tile128 : c.tile64;
+  if (sym) return launch_stencil<T, MODE_MEC>(c.g->view, t, c.omega, op, c.s);
+  return launch_stencil<T, MODE_D>(c.g->view, t, c.omega, op, c.s);
+}
+
+static double node_bytes(const fit_grid* g, int vec_passes, size_t elem) {
+  return (double)g->view.np * 3.0 * elem * vec_passes + (double)g->view.ncx * g->view.ncy * g->view.ncz;
+}
+
+// r = b - A x (unscaled complex128), ||r||^2 -> c.red->v[0]; optional c64 copy.
+static fit_status residual(Ctx& c, const double* x, const double* b, double* r, float* r32,
+                           double r32_scale) {
+  OpResidual<double> op{x, b, r, r32, r32_scale, c.red, c.part, c.cnt};
+  c.bytes += node_bytes(c.g, 2 + (r ? 1 : 0), 16) + (r32 ? (double)c.g->ne * 8 : 0.0);
+  c.matvecs += 1;
+  return launch_op_stencil_mode<double>(c, false, op);
+}
+
+template <class TI, class TO, int KIND>
+static fit_status xform(Ctx& c, bool sym, bool inverse, const TI* in, TO* out, double factor,
+                        bool reduce) {
+  hipLaunchKernelGGL((node_xform_kernel<TI, TO, KIND>), dim3(pw_blocks(c.g->view.np)), dim3(256), 0,
+                     c.s, c.g->view, c.omega, sym ? 1 : 0, inverse ? 1 : 0, in, out, factor,
+                     reduce ? c.red : nullptr, c.part, c.cnt);
+  FIT_HIP(hipGetLastError());
+  c.bytes += (double)c.g->ne * (sizeof(TI) + sizeof(TO)) * 2 * (KIND == XF_AXPY ? 1.5 : 1.0);
+  return FIT_OK;
+}
+
+template <class T>
+static fit_status vzero(Ctx& c, T* v, int64_t ncomplex) {
+  hipLaunchKernelGGL(zero_kernel<T>, dim3(pw_blocks(2 * ncomplex)), dim3(256), 0, c.s, v,
+                     2 * ncomplex);
+  FIT_HIP(hipGetLastError());
+  return FIT_OK;
+}
+template <class T>
+static fit_status vcopy(Ctx& c, const T* a, T* b, int64_t ncomplex) {
+  hipLaunchKernelGGL(copy_kernel<T>, dim3(pw_blocks(2 * ncomplex)), dim3(256), 0, c.s, a, b,
+                     2 * ncomplex);
+  FIT_HIP(hipGetLastError());
+  return FIT_OK;
+}
+
+static fit_status sync_copy(Ctx& c, void* dst, const void* src, size_t bytes) {
+  FIT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.s));
+  FIT_HIP(hipStreamSynchronize(c.s));
+  return FIT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab on A_int x = r0 (A_int = S A S when sym), starting from x = 0.
+// The caller supplies r0 in `r` (overwritten).  Returns the device done code
+// through *done and the iteration count through *iters.
+// ---------------------------------------------------------------------------
+template <class T>
+struct BiVecs {
+  T *x, *r, *rh, *p[2], *v[2], *s, *t;
+};
+
+template <class T>
+static fit_status bicgstab(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int check_every,
+                           double hscale, double* hist_dev, int hist_len, int use_graph,
+                           int* done, int* iters, double* rr_out) {
+  const int64_t ne = c.g->ne;
+  fit_status st;
+  if ((st = vzero(c, V.x, ne)) != FIT_OK) return st;
+  if ((st = vzero(c, V.p[0], ne)) != FIT_OK) return st;
+  if ((st = vzero(c, V.v[0], ne)) != FIT_OK) return st;
+  // Shadow vector: dense pseudo-random on the free edges.  (The textbook
+  // choice r_hat = r_0 collapses for lumped-port sources: r_0 lives on a
+  // handful of edges and <r_hat, r_k> soon vanishes relative to |r_k|.)
+  if ((st = xform<T, T, XF_SHADOW>(c, false, false, V.r, V.rh, 1.0, false)) != FIT_OK) return st;
+  hipLaunchKernelGGL(dot_kernel<T>, dim3(pw_blocks(ne)), dim3(256), 0, c.s, V.rh, V.r, ne, c.red,
+                     c.part, c.cnt);
+  FIT_HIP(hipGetLastError());
+  if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+  const cx<double> rho0{c.h_red->v[0], c.h_red->v[1]};
+  const double rhrh = c.h_red->v[2];
+  const double r0 = c.h_red->v[3];
+  *iters = 0;
+  *rr_out = r0;
+  if (!(r0 > 0.0) || !std::isfinite(r0)) {
+    *done = r0 == 0.0 ? kConverged : kNan;
+    return FIT_OK;
+  }
+  BiState h{};
+  h.rho = rho0;
+  h.alpha = cx<double>{1.0, 0.0};
+  h.omega = cx<double>{1.0, 0.0};
+  h.beta = cx<double>{0.0, 0.0};
+  h.rr = r0;
+  h.rhrh = rhrh;
+  h.tol2 = tol_rel * tol_rel * r0;
+  h.hscale = hscale;
+  h.iter = 0;
+  h.max_iter = max_iter;
+  h.done = kRunning;
+  h.hist = hist_dev;
+  h.hist_len = hist_len;
+  FIT_HIP(hipMemcpyAsync(c.bst, &h, sizeof(BiState), hipMemcpyHostToDevice, c.s));
+
+  const int64_t nb = pw_blocks(ne);
+  auto one_iter = [&](int parity) -> fit_status {
+    T* p_old = V.p[parity];
+    T* p_new = V.p[parity ^ 1];
+    T* v_old = V.v[parity];
+    T* v_new = V.v[parity ^ 1];
+    OpBicgP<T> k1{V.r, p_old, v_old, V.rh, p_new, v_new, c.bst, c.part, c.cnt, {}, {}};
+    fit_status e = launch_op_stencil_mode<T>(c, c.sym, k1);
+    if (e != FIT_OK) return e;
+    OpBicgS<T> k2{V.r, v_new, V.s, V.t, c.bst, c.part, c.cnt, {}};
+    e = launch_op_stencil_mode<T>(c, c.sym, k2);
+    if (e != FIT_OK) return e;
+    hipLaunchKernelGGL(bicg_update_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, V.x, V.r,
+                       p_new, V.s, V.t, V.rh, ne, c.bst, c.part, c.cnt);
+    FIT_HIP(hipGetLastError());
+    return FIT_OK;
+  };
+  const double per_iter_bytes = node_bytes(c.g, 17, sizeof(T)) + node_bytes(c.g, 0, 0) * 1.0;
+  if (check_every <= 0) check_every = 2 * std::max(1, std::min(50, (int)(2e8 / (double)ne)));
+  if (check_every & 1) ++check_every;  // ping-pong parity returns to 0
+
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (use_graph) {
+    // Capture on a private stream (the null stream cannot be captured); the
+    // instantiated graph is then launched in order on the caller's stream.
+    hipStream_t cap = nullptr;
+    FIT_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    const hipStream_t user = c.s;
+    c.s = cap;
+    hipError_t he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    fit_status e = he == hipSuccess ? FIT_OK : hip_fail(he, "hipStreamBeginCapture");
+    for (int q = 0; q < check_every && e == FIT_OK; ++q) e = one_iter(q & 1);
+    if (he == hipSuccess) he = hipStreamEndCapture(cap, &graph);
+    c.s = user;
+    (void)hipStreamDestroy(cap);
+    if (e != FIT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return e;
+    }
+    if (he != hipSuccess) return hip_fail(he, "hipStreamEndCapture");
+    he = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(he, "hipGraphInstantiate");
+    }
+  }
+  int last_iter = 0;
+  fit_status ret = FIT_OK;
+  double best_rr = r0;
+  int best_at = 0;
+  bool stalled = false;
+  const int stall_window = sizeof(T) == 4 ? 1500 : 6000;
+  for (;;) {
+    if (use_graph) {
+      hipError_t he = hipGraphLaunch(gexec, c.s);
+      if (he != hipSuccess) {
+        ret = hip_fail(he, "hipGraphLaunch");
+        break;
+      }
+    } else {
+      for (int q = 0; q < check_every; ++q)
+        if ((ret = one_iter(q & 1)) != FIT_OK) break;
+      if (ret != FIT_OK) break;
+    }
+    if ((ret = sync_copy(c, c.h_bst, c.bst, sizeof(BiState))) != FIT_OK) break;
+    c.bytes += per_iter_bytes * (c.h_bst->iter - last_iter);
+    c.matvecs += 2 * (c.h_bst->iter - last_iter);
+    last_iter = c.h_bst->iter;
+    if (c.h_bst->done != kRunning) break;
+    // Stagnation: no halving of the recursive residual within the window.
+    // Stop here; the caller restarts from the current iterate with a fresh
+    // shadow vector (or falls back to complex128 in the mixed form).
+    if (c.h_bst->rr < 0.25 * best_rr) {
+      best_rr = c.h_bst->rr;
+      best_at = c.h_bst->iter;
+    } else if (c.h_bst->iter - best_at >= stall_window) {
+      stalled = true;
+      break;
+    }
+  }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (ret != FIT_OK) return ret;
+  *done = stalled ? kBreakdown : c.h_bst->done;
+  c.last_reason = stalled ? 9 : c.h_bst->reason;
+  c.last_rr = c.h_bst->rr / r0;
+  *iters = c.h_bst->iter;
+  *rr_out = c.h_bst->rr;
+  // The last step ends with p in p[parity] where parity = iter & 1; after an
+  // odd number of iterations the fresh p lives in p[1].  x and r are final.
+  return FIT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Restarted (F)GMRES(m) on A_int x = r0 from x = 0 (r0 in w0, overwritten).
+// ---------------------------------------------------------------------------
+template <class T>
+struct GmVecs {
+  T* x;
+  T* V;   // (m+1) basis vectors, stride ldv complex
+  T* Z;   // m preconditioned directions (FGMRES) or null
+  T* W[2];
+  int64_t ldv;
+  double* mdpart;  // multi-dot partials (m+1) * nblk complex
+};
+
+template <class T>
+static fit_status gmres(Ctx& c, GmVecs<T>& V, int m, double tol_rel, int max_iter,
+                        double hscale, double* hist_dev, int hist_len, PrecondApply* pre,
+                        const T* r0, const double* b128, int* done, int* iters, double* rel_est,
+                        double r0norm_abs) {
+  const int64_t ne = c.g->ne;
+  fit_status st;
+  if ((st = vzero(c, V.x, ne)) != FIT_OK) return st;
+  // w0 = r0; beta = ||r0||
+  if ((st = vcopy(c, r0, V.W[0], ne)) != FIT_OK) return st;
+  if ((st = xform<T, T, XF_SCALE>(c, false, false, V.W[0], V.W[0], 1.0, true)) != FIT_OK) return st;
+  if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+  double beta = std::sqrt(c.h_red->v[0]);
+  const double target = tol_rel * beta;
+  int it = 0;
+  *done = kRunning;
+  const int nblk_md = (int)((ne + 256 * kMdPer - 1) / (256 * kMdPer));
+  int cur = 0;
+  while (true) {
+    if (!(beta > 0.0)) {
+      *done = beta == 0.0 ? kConverged : kNan;
+      break;
+    }
+    GmState h;
+    std::memset(&h, 0, sizeof(h));
+    h.m = m;
+    h.j = 0;
+    h.k = 0;
+    h.g[0] = cx<double>{beta, 0.0};
+    h.vscale = 1.0 / beta;
+    h.beta = beta;
+    h.tol = target;
+    h.hscale = hscale;
+    h.iter = it;
+    h.max_iter = max_iter;
+    h.done = kRunning;
+    h.hist = hist_dev;
+    h.hist_len = hist_len;
+    FIT_HIP(hipMemcpyAsync(c.gst, &h, sizeof(GmState), hipMemcpyHostToDevice, c.s));
+    for (int j = 0; j < m; ++j) {
+      T* vj = V.V + 2 * V.ldv * j;
+      T* wcur = V.W[cur];
+      T* wnext = V.W[cur ^ 1];
+      if (pre) {
+        // FGMRES: v_j = w * vscale (separately), z_j = M(v_j), w' = A z_j
+        hipLaunchKernelGGL(gm_normalize_kernel<T>, dim3(pw_blocks(ne)), dim3(256), 0, c.s, wcur,
+                           vj, ne, c.gst);
+        FIT_HIP(hipGetLastError());
+        T* zj = V.Z + 2 * V.ldv * j;
+        if ((st = pre->apply(c, vj, zj, sizeof(T) == 4)) != FIT_OK) return st;
+        OpGmresMv<T> mv{zj, nullptr, wnext, c.gst, T(1)};
+        if ((st = launch_op_stencil_mode<T>(c, c.sym, mv)) != FIT_OK) return st;
+        c.bytes += (double)ne * sizeof(T) * 2 * 3;
+      } else {
+        OpGmresMv<T> mv{wcur, vj, wnext, c.gst, T(1)};
+        if ((st = launch_op_stencil_mode<T>(c, c.sym, mv)) != FIT_OK) return st;
+      }
+      c.matvecs += 1;
+      c.bytes += node_bytes(c.g, 3, sizeof(T));
+      // CGS2: two rounds of multi-dot + update
+      for (int round = 0; round < 2; ++round) {
+        hipLaunchKernelGGL(multidot_kernel<T>, dim3(nblk_md), dim3(256), 0, c.s, V.V, V.ldv,
+                           j + 1, wnext, ne, V.mdpart, c.gst);
+        FIT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(multidot_finish_kernel, dim3(j + 1), dim3(256), 0, c.s, V.mdpart,
+                           nblk_md, c.gst, round);
+        FIT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(multi_axpy_kernel<T>, dim3(pw_blocks(ne)), dim3(256), 0, c.s, V.V,
+                           V.ldv, j + 1, wnext, ne, c.gst, round == 1 ? c.red : nullptr, c.part,
+                           c.cnt);
+        FIT_HIP(hipGetLastError());
+        c.bytes += (double)ne * sizeof(T) * 2 * ((j + 2) + (j + 3));
+      }
+      hipLaunchKernelGGL(gmres_step_kernel, dim3(1), dim3(64), 0, c.s, c.gst, c.red);
+      FIT_HIP(hipGetLastError());
+      cur ^= 1;
+      // Poll every few steps so converged cycles end early.
+      if ((j & 7) == 7 || j == m - 1) {
+        if ((st = sync_copy(c, c.h_gst, c.gst, sizeof(GmState))) != FIT_OK) return st;
+        if (c.h_gst->done != kRunning) break;
+      }
+    }
+    if ((st = sync_copy(c, c.h_gst, c.gst, sizeof(GmState))) != FIT_OK) return st;
+    it = c.h_gst->iter;
+    const int code = c.h_gst->done;
+    const int k = c.h_gst->k;
+    if (k > 0) {
+      hipLaunchKernelGGL(gmres_solve_kernel, dim3(1), dim3(64), 0, c.s, c.gst);
+      FIT_HIP(hipGetLastError());
+      hipLaunchKernelGGL(gmres_update_kernel<T>, dim3(pw_blocks(ne)), dim3(256), 0, c.s, V.x,
+                         pre ? V.Z : V.V, V.ldv, ne, c.gst);
+      FIT_HIP(hipGetLastError());
+      c.bytes += (double)ne * sizeof(T) * 2 * (k + 2);
+    }
+    *rel_est = std::sqrt(cabs2(c.h_gst->g[k])) / (beta > 0 ? beta : 1.0);
+    if (code == kConverged || code == kNan || code == kMaxIter) {
+      *done = code;
+      break;
+    }
+    // restart: recompute the internal residual w = r0 - A_int x
+    hipLaunchKernelGGL(gm_restart_prep_kernel, dim3(1), dim3(64), 0, c.s, c.gst);
+    FIT_HIP(hipGetLastError());
+    OpGmresMv<T> mv{V.x, nullptr, V.W[0], c.gst, T(1)};
+    if ((st = launch_op_stencil_mode<T>(c, c.sym, mv)) != FIT_OK) return st;
+    c.matvecs += 1;
+    hipLaunchKernelGGL(sub_norm_kernel<T>, dim3(pw_blocks(ne)), dim3(256), 0, c.s, r0, V.W[0],
+                       ne, c.red, c.part, c.cnt);
+    FIT_HIP(hipGetLastError());
+    if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+    cur = 0;
+    beta = std::sqrt(c.h_red->v[0]);
+    if (beta <= target) {
+      *done = kConverged;
+      break;
+    }
+  }
+  *iters = it;
+  (void)b128;
+  (void)r0norm_abs;
+  return FIT_OK;
+}
+
+// Identity right preconditioner (FGMRES without a learned model).
+struct IdentityPrecond : PrecondApply {
+  fit_status apply(Ctx& c, const void* v, void* z, bool f32) override {
+    if (f32) return vcopy<float>(c, (const float*)v, (float*)z, c.g->ne);
+    return vcopy<double>(c, (const double*)v, (double*)z, c.g->ne);
+  }
+};
+
+// Bump allocator over the grid's workspace arena.
+struct Arena {
+  char* base;
+  size_t off = 0, cap;
+  template <class P>
+  P* take(size_t bytes) {
+    P* p = (P*)(base + off);
+    off += align_up(bytes, 256);
+    return p;
+  }
+};
+
+fit_status setup_ctx(Ctx& c, fit_grid* g, double omega, int sym, hipStream_t s) {
+  c.g = g;
+  c.s = s;
+  c.omega = omega;
+  c.sym = sym;
+  c.tile128 = tile_for(g, FIT_C128);
+  c.tile64 = tile_for(g, FIT_C64);
+  const int b128 = launch_blocks(make_launch(g->view, c.tile128, omega));
+  const int b64 = launch_blocks(make_launch(g->view, c.tile64, omega));
+  c.max_blocks = std::max(std::max(b128, b64), 4096);
+  const size_t need = align_up(sizeof(double) * 4 * (size_t)c.max_blocks, 256) + 256 +
+                      align_up(sizeof(RedOut), 256) + align_up(sizeof(BiState), 256) +
+                      align_up(sizeof(GmState), 256) + align_up(sizeof(CgState), 256);
+  fit_status st = ensure_ws(g->red, need, g->device);
+  if (st != FIT_OK) return st;
+  char* p = (char*)g->red.ptr;
+  c.part = (double*)p;
+  p += align_up(sizeof(double) * 4 * (size_t)c.max_blocks, 256);
+  c.cnt = (unsigned*)p;
+  p += 256;
+  c.red = (RedOut*)p;
+  p += align_up(sizeof(RedOut), 256);
+  c.bst = (BiState*)p;
+  p += align_up(sizeof(BiState), 256);
+  c.gst = (GmState*)p;
+  p += align_up(sizeof(GmState), 256);
+  c.cst = (CgState*)p;
+  if (!g->pinned) {
+    FIT_HIP(hipHostMalloc(&g->pinned, sizeof(RedOut) + sizeof(BiState) + sizeof(GmState) +
+                                          sizeof(CgState) + 256));
+  }
+  char* hp = (char*)g->pinned;
+  c.h_red = (RedOut*)hp;
+  c.h_bst = (BiState*)(hp + sizeof(RedOut));
+  c.h_gst = (GmState*)(hp + sizeof(RedOut) + sizeof(BiState));
+  c.h_cst = (CgState*)(hp + sizeof(RedOut) + sizeof(BiState) + sizeof(GmState));
+  // ticket counter starts at zero; the red block's flag too
+  FIT_HIP(hipMemsetAsync(c.cnt, 0, 256, s));
+  FIT_HIP(hipMemsetAsync(c.red, 0, sizeof(RedOut), s));
+  return FIT_OK;
+}
+
+// Inner solve in precision T on A_int d = rin (rin has unit norm), from d = 0.
+template <class T>
+struct Inner {
+  int solver, m;
+  BiVecs<T> bv;
+  GmVecs<T> gv;
+  T* rin;
+  T* d;
+};
+
+// COCG on A_int x = r (r overwritten), from x = 0; same driver structure as
+// bicgstab(): fused kernels, device scalars, periodic host polls, optional
+// captured graph, stagnation window.
+template <class T>
+static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int check_every,
+                       double hscale, double* hist_dev, int hist_len, int use_graph, int* done,
+                       int* iters) {
+  const int64_t ne = c.g->ne;
+  fit_status st;
+  T* q = V.v[0];
+  if ((st = vzero(c, V.x, ne)) != FIT_OK) return st;
+  if ((st = vzero(c, V.p[0], ne)) != FIT_OK) return st;
+  hipLaunchKernelGGL((dot_kernel<T, true>), dim3(pw_blocks(ne)), dim3(256), 0, c.s, V.r, V.r, ne,
+                     c.red, c.part, c.cnt);
+  FIT_HIP(hipGetLastError());
+  if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+  const cx<double> rho0{c.h_red->v[0], c.h_red->v[1]};
+  const double r0 = c.h_red->v[2];
+  *iters = 0;
+  if (!(r0 > 0.0) || !std::isfinite(r0)) {
+    *done = r0 == 0.0 ? kConverged : kNan;
+    return FIT_OK;
+  }
+  CgState h{};
+  h.rho = rho0;
+  h.beta = cx<double>{0.0, 0.0};
+  h.alpha = cx<double>{0.0, 0.0};
+  h.rr = r0;
+  h.tol2 = tol_rel * tol_rel * r0;
+  h.hscale = hscale / std::sqrt(r0);
+  h.max_iter = max_iter;
+  h.done = kRunning;
+  h.hist = hist_dev;
+  h.hist_len = hist_len;
+  FIT_HIP(hipMemcpyAsync(c.cst, &h, sizeof(CgState), hipMemcpyHostToDevice, c.s));
+  const int64_t nb = pw_blocks(ne);
+  auto one_iter = [&](int parity) -> fit_status {
+    T* p_old = V.p[parity];
+    T* p_new = V.p[parity ^ 1];
+    OpCocgP<T> k1{V.r, p_old, p_new, q, c.cst, c.part, c.cnt, {}};
+    fit_status e = launch_op_stencil_mode<T>(c, c.sym, k1);
+    if (e != FIT_OK) return e;
+    hipLaunchKernelGGL(cocg_update_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, V.x, V.r,
+                       p_new, q, ne, c.cst, c.part, c.cnt);
+    FIT_HIP(hipGetLastError());
+    return FIT_OK;
+  };
+  const double per_iter_bytes = node_bytes(c.g, 10, sizeof(T));
+  if (check_every <= 0) check_every = 2 * std::max(1, std::min(100, (int)(4e8 / (double)ne)));
+  if (check_every & 1) ++check_every;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (use_graph) {
+    hipStream_t cap = nullptr;
+    FIT_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    const hipStream_t user = c.s;
+    c.s = cap;
+    hipError_t he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    fit_status e = he == hipSuccess ? FIT_OK : hip_fail(he, "hipStreamBeginCapture");
+    for (int k = 0; k < check_every && e == FIT_OK; ++k) e = one_iter(k & 1);
+    if (he == hipSuccess) he = hipStreamEndCapture(cap, &graph);
+    c.s = user;
+    (void)hipStreamDestroy(cap);
+    if (e != FIT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return e;
+    }
+    if (he != hipSuccess) return hip_fail(he, "hipStreamEndCapture");
+    he = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(he, "hipGraphInstantiate");
+    }
+  }
+  int last_iter = 0;
+  fit_status ret = FIT_OK;
+  double best_rr = r0;
+  int best_at = 0;
+  bool stalled = false;
+  // COCG residuals oscillate by orders of magnitude before they fall; the
+  // window is wide so only genuine stagnation ends the inner solve.
+  const int stall_window = sizeof(T) == 4 ? 4000 : 30000;
+  for (;;) {
+    if (use_graph) {
+      hipError_t he = hipGraphLaunch(gexec, c.s);
+      if (he != hipSuccess) {
+        ret = hip_fail(he, "hipGraphLaunch");
+        break;
+      }
+    } else {
+      for (int k = 0; k < check_every; ++k)
+        if ((ret = one_iter(k & 1)) != FIT_OK) break;
+      if (ret != FIT_OK) break;
+    }
+    if ((ret = sync_copy(c, c.h_cst, c.cst, sizeof(CgState))) != FIT_OK) break;
+    c.bytes += per_iter_bytes * (c.h_cst->iter - last_iter);
+    c.matvecs += c.h_cst->iter - last_iter;
+    last_iter = c.h_cst->iter;
+    if (c.h_cst->done != kRunning) break;
+    if (c.h_cst->rr < 0.25 * best_rr) {
+      best_rr = c.h_cst->rr;
+      best_at = c.h_cst->iter;
+    } else if (c.h_cst->iter - best_at >= stall_window) {
+      stalled = true;
+      break;
+    }
+  }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (ret != FIT_OK) return ret;
+  *done = stalled ? kBreakdown : c.h_cst->done;
+  *iters = c.h_cst->iter;
+  c.last_reason = stalled ? 9 : c.h_cst->reason;
+  c.last_rr = c.h_cst->rr / r0;
+  return FIT_OK;
+}
+
+template <class T>
+static size_t inner_bytes(int64_t ne, int solver, int m) {
+  const size_t v = align_up((size_t)ne * 2 * sizeof(T), 256);
+  if (solver == FIT_BICGSTAB) return 10 * v;
+  if (solver == FIT_COCG) return 6 * v;
+  const int nblk = (int)((ne + 256 * kMdPer - 1) / (256 * kMdPer));
+  return (size_t)(2 * m + 5) * v + align_up(sizeof(double) * 2 * (size_t)(m + 1) * nblk, 256);
+}
+
+template <class T>
+static void inner_carve(Arena& a, Inner<T>& in, int64_t ne, int solver, int m) {
+  const size_t v = (size_t)ne * 2 * sizeof(T);
+  in.solver = solver;
+  in.m = m;
+  in.rin = a.take<T>(v);
+  if (solver == FIT_BICGSTAB) {
+    in.bv.x = a.take<T>(v);
+    in.bv.r = a.take<T>(v);
+    in.bv.rh = a.take<T>(v);
+    in.bv.p[0] = a.take<T>(v);
+    in.bv.p[1] = a.take<T>(v);
+    in.bv.v[0] = a.take<T>(v);
+    in.bv.v[1] = a.take<T>(v);
+    in.bv.s = a.take<T>(v);
+    in.bv.t = a.take<T>(v);
+    in.d = in.bv.x;
+  } else if (solver == FIT_COCG) {
+    in.bv.x = a.take<T>(v);
+    in.bv.r = a.take<T>(v);
+    in.bv.p[0] = a.take<T>(v);
+    in.bv.p[1] = a.take<T>(v);
+    in.bv.v[0] = a.take<T>(v);
+    in.bv.rh = in.bv.v[1] = in.bv.s = in.bv.t = nullptr;
+    in.d = in.bv.x;
+  } else {
+    const size_t vv = align_up(v, 256);
+    in.gv.ldv = (int64_t)(vv / (2 * sizeof(T)));
+    in.gv.x = a.take<T>(v);
+    in.gv.V = a.take<T>(vv * (m + 1));
+    in.gv.Z = solver == FIT_FGMRES ? a.take<T>(vv * m) : nullptr;
+    in.gv.W[0] = a.take<T>(v);
+    in.gv.W[1] = a.take<T>(v);
+    const int nblk = (int)((ne + 256 * kMdPer - 1) / (256 * kMdPer));
+    in.gv.mdpart = a.take<double>(sizeof(double) * 2 * (size_t)(m + 1) * nblk);
+    in.d = in.gv.x;
+  }
+}
+
+template <class T>
+static fit_status run_inner(Ctx& c, Inner<T>& in, double q, int max_iter, int check_every,
+                            double hscale, double* hist, int hist_len, int use_graph,
+                            PrecondApply* pre, int* done, int* iters) {
+  double tmp = 0.0;
+  if (in.solver == FIT_BICGSTAB) {
+    fit_status st = vcopy<T>(c, in.rin, in.bv.r, c.g->ne);
+    if (st != FIT_OK) return st;
+    return bicgstab<T>(c, in.bv, q, max_iter, check_every, hscale, hist, hist_len, use_graph,
+                       done, iters, &tmp);
+  }
+  if (in.solver == FIT_COCG) {
+    fit_status st = vcopy<T>(c, in.rin, in.bv.r, c.g->ne);
+    if (st != FIT_OK) return st;
+    return cocg<T>(c, in.bv, q, max_iter, check_every, hscale, hist, hist_len, use_graph, done,
+                   iters);
+  }
+  return gmres<T>(c, in.gv, in.m, q, max_iter, hscale, hist, hist_len, pre, in.rin, nullptr,
+                  done, iters, &tmp, 0.0);
+}
+
+}  // namespace fit
+
+using namespace fit;
+
+namespace {
+
+// FIT_VERBOSE=1 in the environment prints one line per refinement step.
+bool verbose() {
+  static const bool v = [] {
+    const char* e = std::getenv("FIT_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
+
+// Outer loop shared by both precisions: x += ||r|| S d with d from an inner
+// solve on the scaled, normalised residual; stop on the true residual.
+template <class T>
+fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x, double* r,
+                  const double* r_init, double rnorm_init, double tol, const fit_solve_opts& o,
+                  double inner_tol, PrecondApply* pre, double* hist, fit_solve_info& info,
+                  double* relres_out, int* total_iters) {
+  const int64_t ne = c.g->ne;
+  fit_status st;
+  double rnorm = rnorm_init;  // residual of the incoming x
+  const double* rcur = r_init;
+  int iters = 0, refin = 0, stall = 0, breakdowns = 0;
+  double best = 1.0;
+  fit_status result = FIT_E_NOT_CONVERGED;
+  for (;;) {
+    // inner rhs: S r scaled to unit norm, in precision T (S r = eta * rin)
+    if ((st = xform<double, T, XF_SCALE>(c, c.sym, false, rcur, in.rin, 1.0 / rnorm, true)) != FIT_OK)
+      return st;
+    if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+    const double eta = rnorm * std::sqrt(c.h_red->v[0]);
+    if (!(eta > 0.0) || !std::isfinite(eta)) {
+      result = FIT_E_NAN;
+      break;
+    }
+    if ((st = xform<T, T, XF_SCALE>(c, false, false, in.rin, in.rin, rnorm / eta, false)) != FIT_OK)
+      return st;
+    const double rel = rnorm / bnorm;
+    double q = 0.5 * tol / rel;
+    if (sizeof(T) == 4) q = std::max(q, inner_tol);
+    q = std::min(q, 0.5);
+    int done = 0, it = 0;
+    const int budget = o.max_iters - iters;
+    if (budget <= 0) break;
+    const int hoff = std::min(iters, o.resid_history_len);
+    if ((st = run_inner<T>(c, in, q, budget, o.check_every, rel, hist ? hist + hoff : nullptr,
+                           o.resid_history_len - hoff, o.use_graph, pre, &done, &it)) != FIT_OK)
+      return st;
+    iters += it;
+    ++refin;
+    if (done == kNan) {
+      result = FIT_E_NAN;
+      break;
+    }
+    // x += eta S d
+    if ((st = xform<T, double, XF_AXPY>(c, c.sym, false, in.d, x, eta, false)) != FIT_OK) return st;
+    // true residual
+    if ((st = residual(c, x, b, r, nullptr, 0.0)) != FIT_OK) return st;
+    if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+    double rn = std::sqrt(c.h_red->v[0]);
+    if (verbose()) {
+      std::fprintf(stderr,
+                   "[fit] refinement %d (%s): inner exit %d (reason %d, inner relres %.2e) after "
+                   "%d it (target %.1e), true relres %.3e\n",
+                   refin, sizeof(T) == 4 ? "c64" : "c128", done, c.last_reason,
+                   std::sqrt(c.last_rr), it, q, rn / bnorm);
+    }
+    if (!std::isfinite(rn) || rn > rnorm) {
+      // The correction made things worse (an inner solve that broke down
+      // early): undo it and stop this precision's refinement.
+      if ((st = xform<T, double, XF_AXPY>(c, c.sym, false, in.d, x, -eta, false)) != FIT_OK) return st;
+      if ((st = residual(c, x, b, r, nullptr, 0.0)) != FIT_OK) return st;
+      if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+      rn = std::sqrt(c.h_red->v[0]);
+      *relres_out = rn / bnorm;
+      result = std::isfinite(rn) ? FIT_E_BREAKDOWN : FIT_E_NAN;
+      break;
+    }
+    rcur = r;
+    *relres_out = rn / bnorm;
+    if (rn <= tol * bnorm) {
+      result = FIT_OK;
+      rnorm = rn;
+      break;
+    }
+    if (done == kBreakdown && in.solver == FIT_BICGSTAB) ++breakdowns;
+    if (rn / bnorm < 0.5 * best) {
+      best = rn / bnorm;
+      stall = 0;
+      breakdowns = 0;
+    } else {
+      ++stall;
+    }
+    rnorm = rn;
+    if (done == kMaxIter || iters >= o.max_iters) {
+      result = FIT_E_NOT_CONVERGED;
+      break;
+    }
+    if (breakdowns >= 5) {
+      result = FIT_E_BREAKDOWN;
+      break;
+    }
+    if (stall >= 4) {
+      result = FIT_E_NOT_CONVERGED;
+      break;
+    }
+  }
+  info.refinements += refin;
+  *total_iters = iters;
+  (void)ne;
+  return result;
+}
+
+}  // namespace
+
+extern "C" fit_status fit_solve(fit_grid* g, double omega, const void* source_dev, double tol,
+                                const fit_solve_opts* opts, void* x_dev, fit_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!g || !source_dev || !x_dev) {
+    set_error("fit_solve: NULL argument");
+    return FIT_E_INVALID;
+  }
+  if (!(omega > 0.0) || !std::isfinite(omega)) {
+    set_error("fit_solve: omega must be finite and > 0");
+    return FIT_E_INVALID;
+  }
+  if (!(tol > 0.0) || !(tol < 1.0)) {
+    set_error("fit_solve: tol must be in (0, 1)");
+    return FIT_E_INVALID;
+  }
+  fit_solve_opts o{};
+  if (opts) o = *opts;
+  if (o.restart == 0) o.restart = 30;
+  if (o.max_iters <= 0) o.max_iters = 100000;
+  if (o.solver < FIT_BICGSTAB || o.solver > FIT_COCG || o.restart < 1 ||
+      o.restart > kMaxRestart || (o.precision != FIT_PREC_FP64 && o.precision != FIT_PREC_MIXED) ||
+      (o.scaling != FIT_SCALE_NONE && o.scaling != FIT_SCALE_SYM) || o.resid_history_len < 0 ||
+      (o.resid_history_len > 0 && !o.resid_history)) {
+    set_error("fit_solve: invalid options");
+    return FIT_E_INVALID;
+  }
+  if (o.inner_tol <= 0.0) o.inner_tol = 1e-4;
+  DeviceScope dev(g->device);
+  hipStream_t s = (hipStream_t)o.stream;
+  Ctx c;
+  fit_status st = setup_ctx(c, g, omega, o.scaling == FIT_SCALE_SYM, s);
+  if (st != FIT_OK) return st;
+
+  const int64_t ne = g->ne;
+  const size_t v128 = align_up((size_t)ne * 16, 256);
+  const bool mixed = o.precision == FIT_PREC_MIXED;
+  const size_t in_bytes = mixed ? inner_bytes<float>(ne, o.solver, o.restart)
+                                : inner_bytes<double>(ne, o.solver, o.restart);
+  const size_t hist_bytes = align_up(sizeof(double) * (size_t)std::max(o.resid_history_len, 1), 256);
+  if ((st = ensure_ws(g->ws, 2 * v128 + in_bytes + hist_bytes + 4096, g->device)) != FIT_OK) return st;
+  Arena a{(char*)g->ws.ptr, 0, g->ws.bytes};
+  double* b = a.take<double>(v128);
+  double* r = a.take<double>(v128);
+  double* hist = o.resid_history_len > 0 ? a.take<double>(hist_bytes) : nullptr;
+  double* x = (double*)x_dev;
+
+  // b = -j omega j, ||b||^2, masked-source check
+  FIT_HIP(hipMemsetAsync(c.red, 0, sizeof(RedOut), s));
+  if ((st = xform<double, double, XF_RHS>(c, false, false, (const double*)source_dev, b, 1.0, true)) != FIT_OK)
+    return st;
+  if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+  if (c.h_red->flag) {
+    set_error("fit_solve: nonzero source on a masked edge");
+    return FIT_E_INVALID;
+  }
+  const double bnorm = std::sqrt(c.h_red->v[0]);
+  if ((st = vzero<double>(c, x, ne)) != FIT_OK) return st;
+  fit_solve_info inf{};
+  double relres = 1.0;
+  int iters = 0;
+  fit_status result;
+  IdentityPrecond ident;
+  PrecondApply* pre = nullptr;
+  if (o.solver == FIT_FGMRES) pre = o.precond ? precond_apply_of(o.precond, g, omega) : &ident;
+  if (!std::isfinite(bnorm)) {
+    result = FIT_E_NAN;
+  } else if (bnorm == 0.0) {
+    result = FIT_OK;
+    relres = 0.0;
+  } else if (mixed) {
+    Inner<float> in;
+    inner_carve<float>(a, in, ne, o.solver, o.restart);
+    result = refine<float>(c, in, b, bnorm, x, r, b, bnorm, tol, o, o.inner_tol, pre, hist, inf,
+                           &relres, &iters);
+    if ((result == FIT_E_NOT_CONVERGED || result == FIT_E_BREAKDOWN || result == FIT_E_NAN) &&
+        iters < o.max_iters) {
+      // complex64 stagnated: continue in complex128 from the current x
+      inf.fell_back = 1;
+      Arena a2{(char*)g->ws.ptr, 0, g->ws.bytes};
+      (void)a2.take<double>(v128);
+      (void)a2.take<double>(v128);
+      if (hist) (void)a2.take<double>(hist_bytes);
+      if ((st = ensure_ws(g->ws, 2 * v128 + inner_bytes<double>(ne, o.solver, o.restart) + hist_bytes + 4096,
+                          g->device)) != FIT_OK)
+        return st;
+      // workspace may have moved: recompute b and r from scratch
+      Arena a3{(char*)g->ws.ptr, 0, g->ws.bytes};
+      b = a3.take<double>(v128);
+      r = a3.take<double>(v128);
+      hist = o.resid_history_len > 0 ? a3.take<double>(hist_bytes) : nullptr;
+      if ((st = xform<double, double, XF_RHS>(c, false, false, (const double*)source_dev, b, 1.0, true)) != FIT_OK)
+        return st;
+      Inner<double> in2;
+      inner_carve<double>(a3, in2, ne, o.solver, o.restart);
+      // continue: the driver restarts from the residual of the current x
+      fit_solve_opts o2 = o;
+      o2.max_iters = o.max_iters - iters;
+      int it2 = 0;
+      // x already holds the mixed-precision iterate; refine it further
+      if ((st = residual(c, x, b, r, nullptr, 0.0)) != FIT_OK) return st;
+      if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+      result = refine<double>(c, in2, b, bnorm, x, r, r, std::sqrt(c.h_red->v[0]), tol, o2,
+                              o.inner_tol, pre, nullptr, inf, &relres, &it2);
+      iters += it2;
+    }
+  } else {
+    Inner<double> in;
+    inner_carve<double>(a, in, ne, o.solver, o.restart);
+    result = refine<double>(c, in, b, bnorm, x, r, b, bnorm, tol, o, o.inner_tol, pre, hist, inf,
+                            &relres, &iters);
+  }
+  if (pre && pre != &ident) delete pre;
+  if (hist && o.resid_history) {
+    const int n = std::min(o.resid_history_len, iters);
+    if (n > 0) FIT_HIP(hipMemcpyAsync(o.resid_history, hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  }
+  FIT_HIP(hipStreamSynchronize(s));
+  const auto t1 = std::chrono::steady_clock::now();
+  inf.status = result;
+  inf.iterations = iters;
+  inf.matvecs = c.matvecs;
+  inf.true_relres = relres;
+  inf.time_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  inf.bytes_moved = c.bytes;
+  if (info) *info = inf;
+  if (result != FIT_OK) {
+    static const char* names[] = {"", "", "", "", "iteration cap reached", "Krylov breakdown",
+                                  "NaN/Inf in the iteration", ""};
+    set_error(std::string("fit_solve: ") + names[result] + " (relres " + std::to_string(relres) + ")");
+  }
+  return result;
+}
+
+// ---------------------------------------------------------------------------
+// Port voltages: u_p = sum of the edge voltages along port p (Sec. IV).
+// ---------------------------------------------------------------------------
+struct PortList {
+  int n;
+  int i[64], j[64], k0[64], k1[64];
+};
+
+__global__ void port_sum_kernel(GridView g, PortList pl, const double* x, int nvec, double* out) {
+  __shared__ double lds[2 * 4];
+  const int p = blockIdx.x, v = blockIdx.y;
+  double acc[2] = {0.0, 0.0};
+  const int64_t off = (int64_t)v * 3 * g.np;
+  for (int k = pl.k0[p] + threadIdx.x; k < pl.k1[p]; k += blockDim.x) {
+    const int64_t n = pl.i[p] + (int64_t)g.nx * (pl.j[p] + (int64_t)g.ny * k);
+    const cx<double> e = ldc(x, off + 3 * n + 2);
+    acc[0] += e.re;
+    acc[1] += e.im;
+  }
+  block_reduce<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    out[2 * ((int64_t)v * pl.n + p)] = acc[0];
+    out[2 * ((int64_t)v * pl.n + p) + 1] = acc[1];
+  }
+}
+
+namespace fit {
+fit_status port_voltages_dev(const fit_grid* g, const void* x_dev, int nvec, double* out_dev,
+                             hipStream_t s) {
+  PortList pl{};
+  pl.n = g->nports;
+  for (int p = 0; p < g->nports; ++p) {
+    const fit_port& q = (*g->host_ports)[p];
+    pl.i[p] = q.i;
+    pl.j[p] = q.j;
+    pl.k0[p] = q.k0;
+    pl.k1[p] = q.k1;
+  }
+  if (pl.n == 0 || nvec == 0) return FIT_OK;
+  hipLaunchKernelGGL(port_sum_kernel, dim3(pl.n, nvec), dim3(64), 0, s, g->view, pl,
+                     (const double*)x_dev, nvec, out_dev);
+  FIT_HIP(hipGetLastError());
+  return FIT_OK;
+}
+}  // namespace fit
+
+extern "C" fit_status fit_port_voltages(const fit_grid* g, const void* x_dev, int nvec,
+                                        double* out_host, void* stream) {
+  if (!g || !x_dev || !out_host || nvec < 1) {
+    set_error("fit_port_voltages: bad argument");
+    return FIT_E_INVALID;
+  }
+  if (g->nports == 0) return FIT_OK;
+  DeviceScope dev(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  double* d = nullptr;
+  const size_t bytes = sizeof(double) * 2 * (size_t)nvec * g->nports;
+  FIT_HIP(hipMalloc(&d, bytes));
+  fit_status st = port_voltages_dev(g, x_dev, nvec, d, s);
+  if (st == FIT_OK) {
+    hipError_t e = hipMemcpyAsync(out_host, d, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "port voltages copy");
+  }
+  (void)hipFree(d);
+  return st;
+}

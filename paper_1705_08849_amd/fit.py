@@ -22,10 +22,10 @@ STATUS_NAMES = ["FIT_OK", "FIT_E_INVALID", "FIT_E_NOMEM", "FIT_E_DEVICE", "FIT_E
                 "FIT_E_BREAKDOWN", "FIT_E_NAN", "FIT_E_UNSUPPORTED"]
 C128, C64 = 0, 1
 SCALE_NONE, SCALE_SYM = 0, 1
-BICGSTAB, GMRES, FGMRES = 0, 1, 2
+BICGSTAB, GMRES, FGMRES, COCG = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
 
-SOLVERS = {"bicgstab": BICGSTAB, "gmres": GMRES, "fgmres": FGMRES}
+SOLVERS = {"bicgstab": BICGSTAB, "gmres": GMRES, "fgmres": FGMRES, "cocg": COCG}
 SCALINGS = {"none": SCALE_NONE, "sym": SCALE_SYM}
 PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
 
