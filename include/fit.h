@@ -252,6 +252,22 @@ fit_status fit_autotune(const struct fit_grid *g, int dtype, int scaling, double
 fit_status fit_tune_save(const char *path);
 fit_status fit_tune_load(const char *path);
 
+/* ---- launch profiler ------------------------------------------------------
+ * While on, every operator launch and every fused Krylov update launch is
+ * bracketed by a HIP event pair on its own stream; fit_profile_stop waits for
+ * the recorded events and returns the summed durations per kernel family
+ * (names such as "cocg_step1", "bicgstab_step1", "matvec"). */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} fit_kernel_stat;
+
+fit_status fit_profile_start(void);
+/* out may be NULL; *n receives the number of families (all of them, even if
+ * more than max). */
+fit_status fit_profile_stop(fit_kernel_stat *out, int max, int *n);
+
 /* ---- learned right preconditioner (3-level 3D U-Net, BF16 MFMA) ---------- */
 
 /* Training configuration for fit_precond_train (all fields have defaults

@@ -372,29 +372,32 @@ def bicgstab(a, b, tol=1e-8, maxiter=100000, x0=None, rhat=None):
     return x, it, float(np.linalg.norm(b - a @ x) / nb)
 
 
-def cocg(a, b, tol=1e-8, maxiter=100000, x0=None, history=False):
+def cocg(a, b, tol=1e-8, maxiter=100000, x0=None, history=False, m=None):
     """Conjugate orthogonal conjugate gradients (van der Vorst & Melissen,
     1990): the CG recurrences with the unconjugated bilinear form x^T y,
-    valid for complex symmetric A.  Stops when ``||r|| <= tol ||b||``
-    (recursive residual, checked against the true one at the end).
-    Returns ``(x, iterations, relres)`` and, with ``history``, the
-    recursive relative residual after every iteration."""
+    valid for complex symmetric A; ``m`` is an optional diagonal
+    (complex symmetric) preconditioner, z = m * r.  Stops when
+    ``||r|| <= tol ||b||`` (recursive residual, checked against the true one
+    at the end).  Returns ``(x, iterations, relres)`` and, with ``history``,
+    the recursive relative residual after every iteration."""
     nb = np.linalg.norm(b)
     x = np.zeros_like(b) if x0 is None else x0.astype(np.complex128).copy()
     r = b - a @ x
     p = np.zeros_like(b)
-    rho = r @ r
+    z = r if m is None else m * r
+    rho = r @ z
     beta = 0.0
     hist = []
     it = 0
     while it < maxiter and np.linalg.norm(r) > tol * nb:
         it += 1
-        p = r + beta * p
+        p = z + beta * p
         q = a @ p
         alpha = rho / (p @ q)
         x = x + alpha * p
         r = r - alpha * q
-        rho_new = r @ r
+        z = r if m is None else m * r
+        rho_new = r @ z
         beta = rho_new / rho
         rho = rho_new
         hist.append(np.linalg.norm(r) / nb)

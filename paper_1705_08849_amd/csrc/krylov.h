@@ -82,7 +82,7 @@ struct OpCocgP {
       acc[1] += pr * yi + pi * yr;
     }
   }
-  __device__ double* partials() const { return part; }
+  __host__ __device__ double* partials() const { return part; }
   __device__ unsigned* counter() const { return cnt; }
   __device__ void finalize(const double* s) const {
     const cx<double> gam{s[0], s[1]};
@@ -188,7 +188,7 @@ struct OpBicgP {
       acc[1] += (double)d.im;
     }
   }
-  __device__ double* partials() const { return part; }
+  __host__ __device__ double* partials() const { return part; }
   __device__ unsigned* counter() const { return cnt; }
   __device__ void finalize(const double* s) const {
     const cx<double> sig{s[0], s[1]};
@@ -253,7 +253,7 @@ struct OpBicgS {
       acc[2] += cabs2_d(y[w]);
     }
   }
-  __device__ double* partials() const { return part; }
+  __host__ __device__ double* partials() const { return part; }
   __device__ unsigned* counter() const { return cnt; }
   __device__ void finalize(const double* sum) const {
     const double tt = sum[2];
@@ -309,7 +309,7 @@ struct OpResidual {
       acc[0] += cabs2_d(rv);
     }
   }
-  __device__ double* partials() const { return part; }
+  __host__ __device__ double* partials() const { return part; }
   __device__ unsigned* counter() const { return cnt; }
   __device__ void finalize(const double* s) const {
     out->v[0] = s[0];
@@ -354,9 +354,30 @@ struct OpGmresMv {
 #pragma unroll
     for (int k = 0; k < 3; ++k) stc(y, 3 * n + k, yv[k]);
   }
-  __device__ double* partials() const { return nullptr; }
+  __host__ __device__ double* partials() const { return nullptr; }
   __device__ unsigned* counter() const { return nullptr; }
   __device__ void finalize(const double*) const {}
+};
+
+template <class T>
+struct OpName<OpCocgP<T>> {
+  static const char* get() { return sizeof(T) == 8 ? "cocg_step1_c128" : "cocg_step1_c64"; }
+};
+template <class T>
+struct OpName<OpBicgP<T>> {
+  static const char* get() { return sizeof(T) == 8 ? "bicgstab_step1_c128" : "bicgstab_step1_c64"; }
+};
+template <class T>
+struct OpName<OpBicgS<T>> {
+  static const char* get() { return sizeof(T) == 8 ? "bicgstab_step2_c128" : "bicgstab_step2_c64"; }
+};
+template <class T>
+struct OpName<OpResidual<T>> {
+  static const char* get() { return "residual_c128"; }
+};
+template <class T>
+struct OpName<OpGmresMv<T>> {
+  static const char* get() { return sizeof(T) == 8 ? "gmres_matvec_c128" : "gmres_matvec_c64"; }
 };
 
 }  // namespace fit

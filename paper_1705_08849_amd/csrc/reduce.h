@@ -2,10 +2,14 @@
 //
 // Every reduction in the library follows one pattern: each thread
 // accumulates in a fixed order, a wavefront folds its 64 lanes with
-// shuffles, the block sums its wavefronts in order and publishes one partial
-// per block; the last block to arrive (atomic ticket) sums the partials in
-// block order.  Results are therefore bitwise reproducible for a fixed launch
-// configuration, which the solver tests rely on.
+// shuffles, the block sums its wavefronts in order and stores one partial
+// per block with plain stores.  A one-block finish kernel launched right
+// after on the same stream sums the partials in block order and runs the
+// scalar update.  The kernel boundary makes the partials visible; no
+// device-scope fence or atomic ticket is used (on a multi-XCD part a
+// device-scope release fence writes back the XCD's L2, which made a ticket
+// per block cost more than the streaming work itself).  Results are bitwise
+// reproducible for a fixed launch configuration.
 #pragma once
 
 #include "fit_internal.h"
@@ -43,42 +47,39 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], double* lds) {
   __syncthreads();
 }
 
-// Publish this block's partial and, in the last block to finish, sum all
-// partials in block order.  Returns true in every thread of that last block;
-// the grid-wide sums are then in `out` of thread 0.  The ticket counter is
-// reset by the last block so the next launch (or graph replay) starts at 0.
+// Store this block's partial sums at partials[block * N + q].
 template <int N>
-__device__ __forceinline__ bool grid_reduce(double (&v)[N], double* partials, unsigned* counter,
-                                            double* lds, double (&out)[N]) {
-  __shared__ int s_last;
+__device__ __forceinline__ void block_partial(double (&v)[N], double* partials, double* lds) {
   block_reduce<N>(v, lds);
-  const int nblk = gridDim.x * gridDim.y * gridDim.z;
-  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   if (threadIdx.x == 0) {
+    const int64_t bid = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
 #pragma unroll
-    for (int q = 0; q < N; ++q) partials[(int64_t)bid * N + q] = v[q];
-    __threadfence();
-    unsigned t = atomicAdd(counter, 1u);
-    s_last = (t == (unsigned)(nblk - 1));
+    for (int q = 0; q < N; ++q) partials[bid * N + q] = v[q];
   }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
+}
+
+// Finish kernel: one block sums nblk partials in block order and hands the
+// totals to f (thread 0).  F provides skip() (nothing was reduced) and
+// operator()(const double* sums).
+template <int N, class F>
+__global__ void __launch_bounds__(256) finish_kernel(const double* partials, int nblk, F f) {
+  __shared__ double lds[N * 4];
+  if (f.skip()) return;
   double s[N];
 #pragma unroll
   for (int q = 0; q < N; ++q) s[q] = 0.0;
-  const volatile double* vp = partials;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
 #pragma unroll
-    for (int q = 0; q < N; ++q) s[q] += vp[(int64_t)b * N + q];
+    for (int q = 0; q < N; ++q) s[q] += partials[(int64_t)b * N + q];
   }
   block_reduce<N>(s, lds);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) out[q] = s[q];
-    atomicExch(counter, 0u);
-  }
-  return true;
+  if (threadIdx.x == 0) f(s);
+}
+
+template <int N, class F>
+inline hipError_t launch_finish(const double* partials, int nblk, const F& f, hipStream_t s) {
+  hipLaunchKernelGGL((finish_kernel<N, F>), dim3(1), dim3(256), 0, s, partials, nblk, f);
+  return hipGetLastError();
 }
 
 }  // namespace fit

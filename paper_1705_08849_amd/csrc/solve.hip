@@ -100,12 +100,20 @@ __global__ void __launch_bounds__(256)
   }
   if (red) {
     if (bad) atomicOr(&red->flag, 1);
-    double outv[1];
-    if (grid_reduce<1>(acc, part, cnt, lds, outv)) {
-      if (threadIdx.x == 0) red->v[0] = outv[0];
-    }
+    block_partial<1>(acc, part, lds);
   }
+  (void)cnt;
 }
+
+// Stores grid-wide sums into a RedOut.
+template <int N>
+struct StoreSums {
+  RedOut* out;
+  __device__ bool skip() const { return false; }
+  __device__ void operator()(const double* s) const {
+    for (int q = 0; q < N; ++q) out->v[q] = s[q];
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Element-wise vector kernels.
@@ -147,8 +155,16 @@ __global__ void __launch_bounds__(256)
     acc[1] += d.im;
     acc[2] += cabs2_d(rv);
   }
-  double sum[3];
-  if (grid_reduce<3>(acc, part, cnt, lds, sum) && threadIdx.x == 0) {
+  block_partial<3>(acc, part, lds);
+  (void)cnt;
+}
+
+// Scalar step after the BiCGStab update's reduction: next beta and rho and
+// the termination tests.
+struct BicgFinish {
+  BiState* st;
+  __device__ bool skip() const { return *(volatile int*)&st->done != kRunning; }
+  __device__ void operator()(const double* sum) const {
     const cx<double> rho_new{sum[0], sum[1]};
     const double rr = sum[2];
     st->iter += 1;
@@ -180,7 +196,7 @@ __global__ void __launch_bounds__(256)
     st->rho = rho_new;
     if (st->iter >= st->max_iter) st->done = kMaxIter;
   }
-}
+};
 
 // Multi-dot h_i = <V_i, w>, i < nv: each block keeps its chunk of w in
 // registers and walks the basis vectors; partials[i * nblk + blk].
@@ -258,10 +274,8 @@ __global__ void __launch_bounds__(256)
     stc(w, e, v);
     acc[0] += cabs2_d(v);
   }
-  if (out) {
-    double s[1];
-    if (grid_reduce<1>(acc, part, cnt, lds, s) && threadIdx.x == 0) out->v[0] = s[0];
-  }
+  if (out) block_partial<1>(acc, part, lds);
+  (void)cnt;
 }
 
 // Completes Arnoldi step j: h_{j+1,j} = ||w||, applies the previous Givens
@@ -365,8 +379,15 @@ __global__ void __launch_bounds__(256)
     acc[1] += 2.0 * rr * ri;
     acc[2] += rr * rr + ri * ri;
   }
-  double sum[3];
-  if (grid_reduce<3>(acc, part, cnt, lds, sum) && threadIdx.x == 0) {
+  block_partial<3>(acc, part, lds);
+  (void)cnt;
+}
+
+// Scalar step after the COCG update's reduction.
+struct CocgFinish {
+  CgState* st;
+  __device__ bool skip() const { return *(volatile int*)&st->done != kRunning; }
+  __device__ void operator()(const double* sum) const {
     const cx<double> rho_new{sum[0], sum[1]};
     const double rr = sum[2];
     st->iter += 1;
@@ -392,7 +413,82 @@ __global__ void __launch_bounds__(256)
     st->rho = rho_new;
     if (st->iter >= st->max_iter) st->done = kMaxIter;
   }
+};
+
+// The diagonal preconditioner of the mass-preconditioned COCG:
+// m = 1/M_eps,c per free edge (0 on masked edges) -- the square of the
+// symmetric scaling S, from the same per-edge rule as the operator.
+template <class T>
+__global__ void __launch_bounds__(256)
+    mass_inverse_kernel(GridView g, double omega, T* m_out) {
+  __shared__ MatLds<double> mat;
+  fill_mat_mode<double>(mat, g.mats, omega, MODE_MEC);
+  const cx<double> pc = port_coef_mode<double>(omega, MODE_MEC);
+  __syncthreads();
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.np;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(n % g.nx);
+    const int j = (int)((n / g.nx) % g.ny);
+    const int k = (int)(n / ((int64_t)g.nx * g.ny));
+    const ColGeo<double> cg = col_geo<double>(g, i, j);
+    const PlaneRec<double> lo = plane_rec(mat, cg, load_cell_ids(g, i, j, k - 1));
+    const PlaneRec<double> hi = plane_rec(mat, cg, load_cell_ids(g, i, j, k));
+    const ZGeo<double> zg = zgeo<double>(g, k);
+    const NodeCoef<double> nc = node_coef(cg, lo, hi, zg.hzl, zg.hzh, zg.ivz, k, pc);
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      cx<T> mv{T(0), T(0)};
+      if ((nc.mask >> w) & 1u) {
+        const cx<double> me = nc.e[w];
+        const double m2 = cabs2(me);
+        mv = cx<T>{(T)(me.re / m2), (T)(-me.im / m2)};
+      }
+      stc(m_out, 3 * n + w, mv);
+    }
+  }
 }
+
+// Mass-preconditioned COCG step 2: x += alpha p, r -= alpha q, z = m .* r,
+// r^T z and ||r||^2.  COCG preconditioned by S^2 produces the iterates of
+// COCG on S A S while the operator itself runs unscaled.  INIT: only
+// z = m .* r and the sums.
+template <class T, bool INIT>
+__global__ void __launch_bounds__(256)
+    pcocg_update_kernel(int64_t n, T* x, T* r, T* z, const T* p, const T* q, const T* m,
+                        CgState* st, double* part) {
+  __shared__ double lds[3 * 4];
+  if (*(volatile int*)&st->done != kRunning) return;
+  const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    cx<T> rv = ldc(r, e);
+    if (!INIT) {
+      stc(x, e, ldc(x, e) + al * ldc(p, e));
+      rv = rv - al * ldc(q, e);
+      stc(r, e, rv);
+    }
+    const cx<T> zv = ldc(m, e) * rv;
+    stc(z, e, zv);
+    const double rr = rv.re, ri = rv.im, zr = zv.re, zi = zv.im;
+    acc[0] += rr * zr - ri * zi;
+    acc[1] += rr * zi + ri * zr;
+    acc[2] += rr * rr + ri * ri;
+  }
+  block_partial<3>(acc, part, lds);
+}
+
+// Initial scalars of the mass-preconditioned COCG: rho = r^T z, ||r||^2.
+struct PcocgInitFinish {
+  CgState* st;
+  __device__ bool skip() const { return false; }
+  __device__ void operator()(const double* sum) const {
+    st->rho = cx<double>{sum[0], sum[1]};
+    st->rr = sum[2];
+    st->beta = cx<double>{0.0, 0.0};
+    if (!isfinite(sum[0]) || !isfinite(sum[1]) || !isfinite(sum[2])) st->done = kNan;
+  }
+};
 
 // <a, b> (or the bilinear a^T b), ||a||^2, ||b||^2 -> out->v[0..3].
 template <class T, bool BILINEAR = false>
@@ -409,10 +505,9 @@ __global__ void __launch_bounds__(256)
     acc[2] += cabs2_d(av);
     acc[3] += cabs2_d(bv);
   }
-  double s[4];
-  if (grid_reduce<4>(acc, part, cnt, lds, s) && threadIdx.x == 0) {
-    for (int q = 0; q < 4; ++q) out->v[q] = s[q];
-  }
+  block_partial<4>(acc, part, lds);
+  (void)cnt;
+  (void)out;
 }
 
 // v_j = w * vscale (FGMRES keeps the normalised vector for the preconditioner).
@@ -444,8 +539,9 @@ __global__ void __launch_bounds__(256)
     stc(w, e, v);
     acc[0] += cabs2_d(v);
   }
-  double s[1];
-  if (grid_reduce<1>(acc, part, cnt, lds, s) && threadIdx.x == 0) out->v[0] = s[0];
+  block_partial<1>(acc, part, lds);
+  (void)cnt;
+  (void)out;
 }
 
 // ---------------------------------------------------------------------------
@@ -504,6 +600,7 @@ static fit_status xform(Ctx& c, bool sym, bool inverse, const TI* in, TO* out, d
                      c.s, c.g->view, c.omega, sym ? 1 : 0, inverse ? 1 : 0, in, out, factor,
                      reduce ? c.red : nullptr, c.part, c.cnt);
   FIT_HIP(hipGetLastError());
+  if (reduce) FIT_HIP(launch_finish<1>(c.part, pw_blocks(c.g->view.np), StoreSums<1>{c.red}, c.s));
   c.bytes += (double)c.g->ne * (sizeof(TI) + sizeof(TO)) * 2 * (KIND == XF_AXPY ? 1.5 : 1.0);
   return FIT_OK;
 }
@@ -555,6 +652,7 @@ static fit_status bicgstab(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, i
   hipLaunchKernelGGL(dot_kernel<T>, dim3(pw_blocks(ne)), dim3(256), 0, c.s, V.rh, V.r, ne, c.red,
                      c.part, c.cnt);
   FIT_HIP(hipGetLastError());
+  FIT_HIP(launch_finish<4>(c.part, pw_blocks(ne), StoreSums<4>{c.red}, c.s));
   if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
   const cx<double> rho0{c.h_red->v[0], c.h_red->v[1]};
   const double rhrh = c.h_red->v[2];
@@ -593,9 +691,12 @@ static fit_status bicgstab(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, i
     OpBicgS<T> k2{V.r, v_new, V.s, V.t, c.bst, c.part, c.cnt, {}};
     e = launch_op_stencil_mode<T>(c, c.sym, k2);
     if (e != FIT_OK) return e;
+    const int tok = prof_begin(c.s);
     hipLaunchKernelGGL(bicg_update_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, V.x, V.r,
                        p_new, V.s, V.t, V.rh, ne, c.bst, c.part, c.cnt);
     FIT_HIP(hipGetLastError());
+    prof_end(tok, c.s, sizeof(T) == 8 ? "bicgstab_update_c128" : "bicgstab_update_c64");
+    FIT_HIP(launch_finish<3>(c.part, (int)nb, BicgFinish{c.bst}, c.s));
     return FIT_OK;
   };
   const double per_iter_bytes = node_bytes(c.g, 17, sizeof(T)) + node_bytes(c.g, 0, 0) * 1.0;
@@ -759,6 +860,7 @@ static fit_status gmres(Ctx& c, GmVecs<T>& V, int m, double tol_rel, int max_ite
                            V.ldv, j + 1, wnext, ne, c.gst, round == 1 ? c.red : nullptr, c.part,
                            c.cnt);
         FIT_HIP(hipGetLastError());
+        if (round == 1) FIT_HIP(launch_finish<1>(c.part, pw_blocks(ne), StoreSums<1>{c.red}, c.s));
         c.bytes += (double)ne * sizeof(T) * 2 * ((j + 2) + (j + 3));
       }
       hipLaunchKernelGGL(gmres_step_kernel, dim3(1), dim3(64), 0, c.s, c.gst, c.red);
@@ -796,6 +898,7 @@ static fit_status gmres(Ctx& c, GmVecs<T>& V, int m, double tol_rel, int max_ite
     hipLaunchKernelGGL(sub_norm_kernel<T>, dim3(pw_blocks(ne)), dim3(256), 0, c.s, r0, V.W[0],
                        ne, c.red, c.part, c.cnt);
     FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<1>(c.part, pw_blocks(ne), StoreSums<1>{c.red}, c.s));
     if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
     cur = 0;
     beta = std::sqrt(c.h_red->v[0]);
@@ -880,6 +983,9 @@ struct Inner {
   GmVecs<T> gv;
   T* rin;
   T* d;
+  // true: the inner method applies the symmetric scaling itself (as a
+  // preconditioner) and works on unscaled vectors
+  bool own_scaling = false;
 };
 
 // COCG on A_int x = r (r overwritten), from x = 0; same driver structure as
@@ -897,6 +1003,7 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
   hipLaunchKernelGGL((dot_kernel<T, true>), dim3(pw_blocks(ne)), dim3(256), 0, c.s, V.r, V.r, ne,
                      c.red, c.part, c.cnt);
   FIT_HIP(hipGetLastError());
+  FIT_HIP(launch_finish<4>(c.part, pw_blocks(ne), StoreSums<4>{c.red}, c.s));
   if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
   const cx<double> rho0{c.h_red->v[0], c.h_red->v[1]};
   const double r0 = c.h_red->v[2];
@@ -918,18 +1025,42 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
   h.hist_len = hist_len;
   FIT_HIP(hipMemcpyAsync(c.cst, &h, sizeof(CgState), hipMemcpyHostToDevice, c.s));
   const int64_t nb = pw_blocks(ne);
+  // With the symmetric scaling requested, COCG runs on the unscaled operator
+  // preconditioned by M = S^2 (z = M r); the iterates equal those of COCG on
+  // S A S, and the operator kernel needs no per-edge square roots.
+  const bool pre = c.sym != 0;
+  T* z = V.s;
+  T* mdiag = V.t;
+  const int64_t nbn = nb;
+  if (pre) {
+    hipLaunchKernelGGL(mass_inverse_kernel<T>, dim3((unsigned)pw_blocks(c.g->view.np)), dim3(256),
+                       0, c.s, c.g->view, c.omega, mdiag);
+    FIT_HIP(hipGetLastError());
+    hipLaunchKernelGGL((pcocg_update_kernel<T, true>), dim3((unsigned)nbn), dim3(256), 0, c.s, ne,
+                       V.x, V.r, z, V.p[0], q, mdiag, c.cst, c.part);
+    FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<3>(c.part, (int)nbn, PcocgInitFinish{c.cst}, c.s));
+  }
   auto one_iter = [&](int parity) -> fit_status {
     T* p_old = V.p[parity];
     T* p_new = V.p[parity ^ 1];
-    OpCocgP<T> k1{V.r, p_old, p_new, q, c.cst, c.part, c.cnt, {}};
-    fit_status e = launch_op_stencil_mode<T>(c, c.sym, k1);
+    OpCocgP<T> k1{pre ? z : V.r, p_old, p_new, q, c.cst, c.part, c.cnt, {}};
+    fit_status e = launch_op_stencil_mode<T>(c, false, k1);
     if (e != FIT_OK) return e;
-    hipLaunchKernelGGL(cocg_update_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, V.x, V.r,
-                       p_new, q, ne, c.cst, c.part, c.cnt);
+    const int tok = prof_begin(c.s);
+    if (pre) {
+      hipLaunchKernelGGL((pcocg_update_kernel<T, false>), dim3((unsigned)nbn), dim3(256), 0, c.s,
+                         ne, V.x, V.r, z, p_new, q, mdiag, c.cst, c.part);
+    } else {
+      hipLaunchKernelGGL(cocg_update_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, V.x, V.r,
+                         p_new, q, ne, c.cst, c.part, c.cnt);
+    }
     FIT_HIP(hipGetLastError());
+    prof_end(tok, c.s, sizeof(T) == 8 ? "cocg_update_c128" : "cocg_update_c64");
+    FIT_HIP(launch_finish<3>(c.part, (int)(pre ? nbn : nb), CocgFinish{c.cst}, c.s));
     return FIT_OK;
   };
-  const double per_iter_bytes = node_bytes(c.g, 10, sizeof(T));
+  const double per_iter_bytes = node_bytes(c.g, pre ? 12 : 10, sizeof(T));
   if (check_every <= 0) check_every = 2 * std::max(1, std::min(100, (int)(4e8 / (double)ne)));
   if (check_every & 1) ++check_every;
   hipGraphExec_t gexec = nullptr;
@@ -1003,7 +1134,7 @@ template <class T>
 static size_t inner_bytes(int64_t ne, int solver, int m) {
   const size_t v = align_up((size_t)ne * 2 * sizeof(T), 256);
   if (solver == FIT_BICGSTAB) return 10 * v;
-  if (solver == FIT_COCG) return 6 * v;
+  if (solver == FIT_COCG) return 8 * v;
   const int nblk = (int)((ne + 256 * kMdPer - 1) / (256 * kMdPer));
   return (size_t)(2 * m + 5) * v + align_up(sizeof(double) * 2 * (size_t)(m + 1) * nblk, 256);
 }
@@ -1031,8 +1162,11 @@ static void inner_carve(Arena& a, Inner<T>& in, int64_t ne, int solver, int m) {
     in.bv.p[0] = a.take<T>(v);
     in.bv.p[1] = a.take<T>(v);
     in.bv.v[0] = a.take<T>(v);
-    in.bv.rh = in.bv.v[1] = in.bv.s = in.bv.t = nullptr;
+    in.bv.s = a.take<T>(v);  // z = M r of the mass-preconditioned form
+    in.bv.t = a.take<T>(v);  // the diagonal M
+    in.bv.rh = in.bv.v[1] = nullptr;
     in.d = in.bv.x;
+    in.own_scaling = true;
   } else {
     const size_t vv = align_up(v, 256);
     in.gv.ldv = (int64_t)(vv / (2 * sizeof(T)));
@@ -1099,7 +1233,7 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
   fit_status result = FIT_E_NOT_CONVERGED;
   for (;;) {
     // inner rhs: S r scaled to unit norm, in precision T (S r = eta * rin)
-    if ((st = xform<double, T, XF_SCALE>(c, c.sym, false, rcur, in.rin, 1.0 / rnorm, true)) != FIT_OK)
+    if ((st = xform<double, T, XF_SCALE>(c, c.sym && !in.own_scaling, false, rcur, in.rin, 1.0 / rnorm, true)) != FIT_OK)
       return st;
     if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
     const double eta = rnorm * std::sqrt(c.h_red->v[0]);
@@ -1127,7 +1261,7 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
       break;
     }
     // x += eta S d
-    if ((st = xform<T, double, XF_AXPY>(c, c.sym, false, in.d, x, eta, false)) != FIT_OK) return st;
+    if ((st = xform<T, double, XF_AXPY>(c, c.sym && !in.own_scaling, false, in.d, x, eta, false)) != FIT_OK) return st;
     // true residual
     if ((st = residual(c, x, b, r, nullptr, 0.0)) != FIT_OK) return st;
     if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
@@ -1142,12 +1276,17 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
     if (!std::isfinite(rn) || rn > rnorm) {
       // The correction made things worse (an inner solve that broke down
       // early): undo it and stop this precision's refinement.
-      if ((st = xform<T, double, XF_AXPY>(c, c.sym, false, in.d, x, -eta, false)) != FIT_OK) return st;
+      if ((st = xform<T, double, XF_AXPY>(c, c.sym && !in.own_scaling, false, in.d, x, -eta, false)) != FIT_OK) return st;
       if ((st = residual(c, x, b, r, nullptr, 0.0)) != FIT_OK) return st;
       if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
       rn = std::sqrt(c.h_red->v[0]);
       *relres_out = rn / bnorm;
-      result = std::isfinite(rn) ? FIT_E_BREAKDOWN : FIT_E_NAN;
+      if (!std::isfinite(rn))
+        result = FIT_E_NAN;
+      else if (done == kMaxIter || iters >= o.max_iters)
+        result = FIT_E_NOT_CONVERGED;
+      else
+        result = FIT_E_BREAKDOWN;
       break;
     }
     rcur = r;

@@ -31,6 +31,7 @@
 #pragma once
 
 #include "fit_internal.h"
+#include "profile.h"
 #include "reduce.h"
 
 namespace fit {
@@ -362,13 +363,17 @@ __global__ void __launch_bounds__(TX* TY)
     __syncthreads();
   }
 
-  if (Op::NRED > 0) {
-    double out[NR];
-    if (grid_reduce<NR>(acc, op.partials(), op.counter(), red_lds, out)) {
-      if (tid == 0) op.finalize(out);
-    }
-  }
+  if (Op::NRED > 0) block_partial<NR>(acc, op.partials(), red_lds);
 }
+
+// Finish functor: hands the grid-wide sums of an Op's reductions to its
+// finalize step (one thread), unless the Op skipped.
+template <class Op>
+struct OpFinish {
+  Op op;
+  __device__ bool skip() const { return op.skip(); }
+  __device__ void operator()(const double* s) const { op.finalize(s); }
+};
 
 // Launch geometry for a grid and tile shape.
 struct TileShape {
@@ -394,6 +399,12 @@ inline bool tile_supported(TileShape t) {
   return t.zc >= 1 && ((t.tx == 64 && (t.ty == 4 || t.ty == 8)) || (t.tx == 32 && t.ty == 8));
 }
 
+// Kernel-family name of an Op for the launch profiler.
+template <class Op>
+struct OpName {
+  static const char* get() { return "stencil"; }
+};
+
 template <class T, int MODE, class Op>
 fit_status launch_stencil(const GridView& g, TileShape t, double omega, const Op& op,
                           hipStream_t s) {
@@ -403,6 +414,7 @@ fit_status launch_stencil(const GridView& g, TileShape t, double omega, const Op
   }
   const StencilLaunch L = make_launch(g, t, omega);
   const dim3 grid((unsigned)launch_blocks(L));
+  const int tok = prof_begin(s);
   if (t.tx == 64 && t.ty == 4)
     hipLaunchKernelGGL((stencil_kernel<T, 64, 4, MODE, Op>), grid, dim3(256), 0, s, g, L, op);
   else if (t.tx == 64 && t.ty == 8)
@@ -410,6 +422,10 @@ fit_status launch_stencil(const GridView& g, TileShape t, double omega, const Op
   else
     hipLaunchKernelGGL((stencil_kernel<T, 32, 8, MODE, Op>), grid, dim3(256), 0, s, g, L, op);
   FIT_HIP(hipGetLastError());
+  prof_end(tok, s, OpName<Op>::get());
+  if constexpr (Op::NRED > 0) {
+    FIT_HIP(launch_finish<Op::NRED>(op.partials(), (int)grid.x, OpFinish<Op>{op}, s));
+  }
   return FIT_OK;
 }
 
@@ -443,9 +459,13 @@ struct OpMatvec {
 #pragma unroll
     for (int w = 0; w < 3; ++w) stc(y, 3 * n + w, yv[w]);
   }
-  __device__ double* partials() const { return nullptr; }
+  __host__ __device__ double* partials() const { return nullptr; }
   __device__ unsigned* counter() const { return nullptr; }
   __device__ void finalize(const double*) const {}
+};
+template <class T>
+struct OpName<OpMatvec<T>> {
+  static const char* get() { return "matvec"; }
 };
 
 }  // namespace fit

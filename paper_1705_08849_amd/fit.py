@@ -72,6 +72,22 @@ class SolveInfo(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+def profile_start():
+    check(lib().fit_profile_start(), "fit_profile_start")
+
+
+def profile_stop():
+    """Per kernel family: {name: (launches, total_ms)} since profile_start()."""
+    n = C.c_int()
+    buf = (KernelStat * 64)()
+    check(lib().fit_profile_stop(buf, 64, C.byref(n)), "fit_profile_stop")
+    return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(n.value, 64))}
+
+
 class PrecondCfg(C.Structure):
     _fields_ = [("base_channels", C.c_int32), ("steps", C.c_int32), ("batch", C.c_int32),
                 ("crop", C.c_int32), ("pairs_per_system", C.c_int32), ("seed", C.c_int32),
@@ -110,6 +126,8 @@ _SIGS = [
                                C.POINTER(C.c_double)]),
     ("fit_tune_save", C.c_int, [C.c_char_p]),
     ("fit_tune_load", C.c_int, [C.c_char_p]),
+    ("fit_profile_start", C.c_int, []),
+    ("fit_profile_stop", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     ("fit_last_error", C.c_char_p, []),
     ("fit_version", C.c_char_p, []),
 ]

@@ -361,6 +361,13 @@ def test_textbook_bicgstab_with_dense_shadow_vector():
     xc, itc, rrc = O.cocg(a, b, tol=1e-10)
     assert rrc <= 3e-10  # recursive residual stops at 1e-10; true one within a small gap
     assert np.linalg.norm(xc - x) <= 1e-6 * np.linalg.norm(x)
+    # COCG on S A S equals COCG on A preconditioned by S^2 (x = S x_hat)
+    a0 = O.system_matrix(dev, om)
+    b0 = O.rhs(dev, om, D.port_source(dev, 0))
+    _, _, _, h_scaled = O.cocg(a, b, tol=1e-30, maxiter=40, history=True)
+    xp, _, _, h_pre = O.cocg(a0, b0, tol=1e-30, maxiter=40, history=True, m=s * s)
+    xh, _, _ = O.cocg(a, b, tol=1e-30, maxiter=40)
+    assert np.linalg.norm(xp - s * xh) <= 1e-8 * np.linalg.norm(xp)
 
 
 # --- Mutation tests: plant mistakes in the oracle, the pins must notice ------
