@@ -232,9 +232,11 @@ fit_status fit_port_voltages(const struct fit_grid *g, const void *x_dev, int nv
                              double *out_host, void *stream);
 
 /* ---- stencil launch shapes and the autotuner ------------------------------
- * The operator kernels tile the node grid into TX x TY columns marching up
- * ZC z-planes.  Compiled shapes: (TX, TY) in {(64,4), (64,8), (32,8)}.  The
- * table is process-wide and keyed by the grid's node dimensions and dtype. */
+ * A workgroup of tx x ty threads covers tx x ty node columns -- the
+ * (tx-2) x (ty-2) columns it outputs plus a one-node halo ring -- and marches
+ * up zc z-planes.  Compiled shapes: (tx, ty) in {(64,8), (48,8), (32,8),
+ * (32,16)}.  The table is process-wide and keyed by the grid's node
+ * dimensions and dtype. */
 
 /* Force a tile shape for grids of g's node dimensions in `dtype`.
  * FIT_E_INVALID for a shape that is not compiled or zc < 1. */

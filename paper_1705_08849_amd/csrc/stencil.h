@@ -14,17 +14,20 @@
 // along the dual edge); nothing per edge is stored.
 //
 // Data movement (MI355X design):
-//  * A workgroup owns a TX x TY tile of node columns and marches up a chunk of
-//    ZC z-planes.  Lanes run along x, so each plane row is one coalesced
-//    48-byte-per-lane (c128) / 24-byte (c64) read; the node records of the
-//    paper's (x, y, z)-interleaved layout are consumed whole.
-//  * One x-plane (tile + 1-node halo ring) lives in LDS; the facets of the
-//    current plane live in LDS for the -x/-y neighbours; the own column's
-//    facets of the previous plane stay in registers; the next plane is
-//    prefetched into registers one step ahead.
+//  * A workgroup of BX x BY threads covers a BX x BY block of node columns:
+//    the (BX-2) x (BY-2) columns it outputs plus a one-node halo ring.  It
+//    marches up a chunk of ZC z-planes.  Each thread owns exactly one column:
+//    it stages that node of every plane (load, mask, material coefficients),
+//    the tile and its low ring compute their three facet fluxes, and the
+//    tile gathers C^T h onto its edges.  Lanes run along x, so every plane
+//    row is one coalesced read of whole (x, y, z)-interleaved node records.
+//  * The current x-plane and the current facets live in LDS; the own
+//    column's facets of the plane below stay in registers; the next plane is
+//    staged in registers one step ahead and its raw data prefetched two.
 //  * Each z-chunk recomputes one plane of facets below it (warm-up), so HBM
-//    reads per node are 1 + 1/ZC plus the halo ring, which neighbouring tiles
-//    scheduled on the same XCD mostly find in L2 (XCD-aware block order).
+//    reads per node are (1 + 1/ZC) times the block's halo overhead, which
+//    neighbouring tiles scheduled on the same XCD mostly find in L2
+//    (XCD-aware block order).
 //  * Krylov vector updates and reductions are fused through the Op policy:
 //    the input may be produced on the fly from several vectors (and written
 //    back for owned nodes), and the output may feed fused dot products.
@@ -86,11 +89,6 @@ struct StencilLaunch {
   int xcd_aware;
 };
 
-template <class T>
-struct C3 {
-  cx<T> c[3];
-};
-
 // Per-plane geometry of z-plane p (uniform over the workgroup).
 template <class T>
 struct ZGeo {
@@ -120,26 +118,6 @@ struct Staged {
   T nu[3];
   uint32_t mask;
 };
-
-// A halo node only feeds the curl: its staged value and facet reluctances.
-template <class T>
-struct HaloStaged {
-  cx<T> xs[3];
-  T nu[3];
-};
-
-template <class T, int MODE>
-__device__ __forceinline__ void stage_halo(HaloStaged<T>& st, const cx<T> (&xin)[3],
-                                           const NodeCoef<T>& nc) {
-#pragma unroll
-  for (int w = 0; w < 3; ++w) {
-    const bool fr = (nc.mask >> w) & 1u;
-    cx<T> xv = fr ? xin[w] : cx<T>{T(0), T(0)};
-    if (MODE == MODE_MEC) xv = fr ? crsqrt(nc.e[w]) * xv : xv;
-    st.xs[w] = xv;
-    st.nu[w] = nc.nu[w];
-  }
-}
 
 template <class T, int MODE>
 __device__ __forceinline__ void stage_node(Staged<T>& st, const cx<T> (&xin)[3],
@@ -174,14 +152,14 @@ __device__ __forceinline__ void stage_node(Staged<T>& st, const cx<T> (&xin)[3],
 //   void own_input(int64_t node, const cx<T> (&xin)[3]) const;   (owned nodes)
 //   void consume(int64_t node, const cx<T> (&y)[3], const cx<T> (&xr)[3],
 //                double* acc) const;                output at owned nodes
-//   void finalize(const double* sums) const;        thread 0 of the last block
+//   double* partials() const;                       block partial sums
+//   void finalize(const double* sums) const;        scalar step (finish kernel)
 // ---------------------------------------------------------------------------
-template <class T, int TX, int TY, int MODE, class Op>
-__global__ void __launch_bounds__(TX* TY)
+template <class T, int BX, int BY, int MODE, class Op>
+__global__ void __launch_bounds__(BX* BY)
     stencil_kernel(GridView g, StencilLaunch L, Op op) {
-  constexpr int NT = TX * TY;
-  constexpr int NH = 2 * TX + 2 * TY + 2;
-  static_assert(NH <= NT, "one halo node per thread");
+  constexpr int TX = BX - 2, TY = BY - 2;
+  constexpr int NT = BX * BY;
   static_assert(NT % 64 == 0, "whole wavefronts");
   constexpr bool SYM = (MODE == MODE_MEC);
   constexpr int NR = Op::NRED > 0 ? Op::NRED : 1;
@@ -190,112 +168,77 @@ __global__ void __launch_bounds__(TX* TY)
   op.begin();
 
   __shared__ MatLds<T> mat;
-  __shared__ cx<T> X[3][TY + 2][TX + 2];
-  __shared__ cx<T> H[3][TY + 1][TX + 1];
+  __shared__ cx<T> X[3][BY][BX];
+  __shared__ cx<T> H[3][BY - 1][BX - 1];
   __shared__ double red_lds[NR * (NT / 64)];
 
   const int tid = threadIdx.x;
-  const int tx = tid % TX, ty = tid / TX;
-  const int nblk = gridDim.x;
-  const int lb = L.xcd_aware ? xcd_remap(blockIdx.x, nblk) : (int)blockIdx.x;
+  const int tx = tid % BX, ty = tid / BX;
+  const int lb = L.xcd_aware ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int bx = lb % L.nbx;
   const int rest = lb / L.nbx;
   const int by = rest % L.nby;
   const int bz = rest / L.nby;
-  const int i0 = bx * TX, j0 = by * TY;
   const int kb = bz * L.zc;
   const int ke = min(kb + L.zc, g.nz);
   const int ks = kb > 0 ? kb - 1 : 0;
 
+  // this thread's node column
+  const int i = bx * TX - 1 + tx, j = by * TY - 1 + ty;
+  const bool inb = i >= 0 && j >= 0 && i < g.nx && j < g.ny;
+  const bool facets = tx <= TX && ty <= TY;               // tile + low halo ring
+  const bool owner = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && inb;  // outputs
+  const int ic = max(i, 0), jc = max(j, 0);
+  const int64_t col = (int64_t)jc * g.nx + ic;
+  const int64_t plane = (int64_t)g.nx * g.ny;
+
   fill_mat_mode<T>(mat, g.mats, L.omega, MODE);
   const cx<T> pcoef = port_coef_mode<T>(L.omega, MODE);
   const T w2 = (T)(L.omega * L.omega);
-
-  // ---- slot 0: the owned node column --------------------------------------
-  const int i_0 = i0 + tx, j_0 = j0 + ty;
-  const bool in0 = (i_0 < g.nx) && (j_0 < g.ny);
-  const ColGeo<T> cg0 = col_geo<T>(g, i_0, j_0);
-  const int64_t col0 = (int64_t)j_0 * g.nx + i_0;
-
-  // ---- slot 1: one node of the halo ring (none for some threads) ---------
-  int hx1 = -1, hy1 = -1;
-  if (tid < NH) {
-    int h = tid;
-    if (h < TX) {
-      hx1 = h + 1; hy1 = 0;                // row below the tile
-    } else if ((h -= TX) < TY) {
-      hx1 = 0; hy1 = h + 1;                // column left of the tile
-    } else if ((h -= TY) < TX) {
-      hx1 = h + 1; hy1 = TY + 1;           // row above
-    } else if ((h -= TX) < TY) {
-      hx1 = TX + 1; hy1 = h + 1;           // column right
-    } else if ((h -= TY) == 0) {
-      hx1 = TX + 1; hy1 = 0;               // corner (+x, -y)
-    } else {
-      hx1 = 0; hy1 = TY + 1;               // corner (-x, +y)
-    }
-  }
-  const bool has1 = hx1 >= 0;
-  const int i_1 = i0 + hx1 - 1, j_1 = j0 + hy1 - 1;
-  const bool in1 = has1 && i_1 >= 0 && j_1 >= 0 && i_1 < g.nx && j_1 < g.ny;
-  const ColGeo<T> cg1 = col_geo<T>(g, max(i_1, 0), max(j_1, 0));
-  const int64_t col1 = (int64_t)max(j_1, 0) * g.nx + max(i_1, 0);
-
-  auto cell_ids = [&](bool inb, int i, int j, int p) -> uint32_t {
-    return inb ? load_cell_ids(g, i, j, p) : 0xFFFFFFFFu;
-  };
-  auto node_of = [&](int64_t col, int p) -> int64_t { return col + (int64_t)p * g.nx * g.ny; };
-
+  const ColGeo<T> cg = col_geo<T>(g, ic, jc);
   __syncthreads();  // material table ready
 
-  // plane records of plane ks-1 (the "lo" plane of the first staged plane)
-  PlaneRec<T> lo0 = plane_rec(mat, cg0, cell_ids(in0, i_0, j_0, ks - 1));
-  PlaneRec<T> lo1 = plane_rec(mat, cg1, cell_ids(in1, i_1, j_1, ks - 1));
+  PlaneRec<T> lo = plane_rec(mat, cg, inb ? load_cell_ids(g, i, j, ks - 1) : 0xFFFFFFFFu);
 
-  Staged<T> s0c, s0n;
-  HaloStaged<T> s1c, s1n;
-  typename Op::Raw raw0, raw1;
-  uint32_t ids0, ids1;
+  typename Op::Raw raw;
+  uint32_t ids = 0xFFFFFFFFu;
+  Staged<T> sn;  // the next plane (staged one step ahead)
+  // the current plane: coefficients and reluctances (its staged values are in LDS)
+  cx<T> cur_cf[3], cur_xr[3];
+  T cur_nu[3];
+  uint32_t cur_mask = 0;
 
   auto fetch = [&](int q) {
-    const bool ok = q < g.nz && q <= ke;
-    if (in0 && ok) op.load(node_of(col0, q), raw0); else op.zero(raw0);
-    if (in1 && ok) op.load(node_of(col1, q), raw1); else op.zero(raw1);
-    ids0 = cell_ids(in0 && q < g.nz, i_0, j_0, q);
-    ids1 = cell_ids(in1 && q < g.nz, i_1, j_1, q);
+    if (inb && q < g.nz && q <= ke) op.load(col + (int64_t)q * plane, raw); else op.zero(raw);
+    ids = (inb && q < g.nz) ? load_cell_ids(g, i, j, q) : 0xFFFFFFFFu;
   };
-  auto process = [&](int q, Staged<T>& d0, HaloStaged<T>& d1) {
+  auto process = [&](int q) {
     const ZGeo<T> z = zgeo<T>(g, q);
-    PlaneRec<T> hi0 = plane_rec(mat, cg0, ids0);
-    NodeCoef<T> nc0 = node_coef(cg0, lo0, hi0, z.hzl, z.hzh, z.ivz, q, pcoef);
-    lo0 = hi0;
+    const PlaneRec<T> hi = plane_rec(mat, cg, ids);
+    const NodeCoef<T> nc = node_coef(cg, lo, hi, z.hzl, z.hzh, z.ivz, q, pcoef);
+    lo = hi;
     cx<T> xin[3];
-    op.input(raw0, xin);
-    stage_node<T, MODE>(d0, xin, nc0);
-    if (in0 && q >= kb && q < ke) op.own_input(node_of(col0, q), d0.xr);
-    if (has1) {
-      PlaneRec<T> hi1 = plane_rec(mat, cg1, ids1);
-      NodeCoef<T> nc1 = node_coef(cg1, lo1, hi1, z.hzl, z.hzh, z.ivz, q, pcoef);
-      lo1 = hi1;
-      op.input(raw1, xin);
-      stage_halo<T, MODE>(d1, xin, nc1);
-    }
+    op.input(raw, xin);
+    stage_node<T, MODE>(sn, xin, nc);
+    if (owner && q >= kb && q < ke) op.own_input(col + (int64_t)q * plane, sn.xr);
   };
-  auto put_x = [&](const Staged<T>& d0, const HaloStaged<T>& d1) {
+  auto advance = [&]() {
 #pragma unroll
-    for (int w = 0; w < 3; ++w) X[w][ty + 1][tx + 1] = d0.xs[w];
-    if (has1) {
-#pragma unroll
-      for (int w = 0; w < 3; ++w) X[w][hy1][hx1] = d1.xs[w];
+    for (int w = 0; w < 3; ++w) {
+      X[w][ty][tx] = sn.xs[w];
+      cur_cf[w] = sn.cf[w];
+      cur_nu[w] = sn.nu[w];
+      if (SYM) cur_xr[w] = sn.xr[w];
     }
+    cur_mask = sn.mask;
   };
 
   // ---- prologue: stage planes ks and ks+1, prefetch ks+2 -----------------
   fetch(ks);
-  process(ks, s0c, s1c);
+  process(ks);
+  advance();
   fetch(ks + 1);
-  process(ks + 1, s0n, s1n);
-  put_x(s0c, s1c);
+  process(ks + 1);
   fetch(ks + 2);
   __syncthreads();
 
@@ -305,60 +248,49 @@ __global__ void __launch_bounds__(TX* TY)
   cx<T> hpx = {T(0), T(0)}, hpy = {T(0), T(0)};  // own facets of the plane below
 
   for (int k = ks; k < ke; ++k) {
-    // ---- C: facets of plane k ---------------------------------------------
-    cx<T> hx, hy, hz;
-    {
-      const cx<T> xz_jp = X[2][ty + 2][tx + 1], xx_jp = X[0][ty + 2][tx + 1];
-      const cx<T> xz_ip = X[2][ty + 1][tx + 2], xy_ip = X[1][ty + 1][tx + 2];
-      hx = s0c.nu[0] * (xz_jp - s0c.xs[2] - s0n.xs[1] + s0c.xs[1]);
-      hy = s0c.nu[1] * (s0n.xs[0] - s0c.xs[0] - xz_ip + s0c.xs[2]);
-      hz = s0c.nu[2] * (xy_ip - s0c.xs[1] - xx_jp + s0c.xs[0]);
-      H[0][ty + 1][tx + 1] = hx;
-      H[1][ty + 1][tx + 1] = hy;
-      H[2][ty + 1][tx + 1] = hz;
-    }
-    if (tid < TX) {
-      // facets (x, z) of node (i0+tid, j0-1): needed by the tile's first row
-      const cx<T> hxh = s1c.nu[0] * (X[2][1][tx + 1] - s1c.xs[2] - s1n.xs[1] + s1c.xs[1]);
-      const cx<T> hzh = s1c.nu[2] * (X[1][0][tx + 2] - s1c.xs[1] - X[0][1][tx + 1] + s1c.xs[0]);
-      H[0][0][tx + 1] = hxh;
-      H[2][0][tx + 1] = hzh;
-    } else if (tid < TX + TY) {
-      // facets (y, z) of node (i0-1, j0+t): needed by the tile's first column
-      const int t = tid - TX;
-      const cx<T> hyh = s1c.nu[1] * (s1n.xs[0] - s1c.xs[0] - X[2][t + 1][1] + s1c.xs[2]);
-      const cx<T> hzh = s1c.nu[2] * (X[1][t + 1][1] - s1c.xs[1] - X[0][t + 2][0] + s1c.xs[0]);
-      H[1][t + 1][0] = hyh;
-      H[2][t + 1][0] = hzh;
+    // ---- C: facets of plane k (tile + low halo ring) ----------------------
+    cx<T> xo[3];
+    cx<T> hx = {T(0), T(0)}, hy = {T(0), T(0)}, hz = {T(0), T(0)};
+#pragma unroll
+    for (int w = 0; w < 3; ++w) xo[w] = X[w][ty][tx];
+    if (facets) {
+      const cx<T> xz_jp = X[2][ty + 1][tx], xx_jp = X[0][ty + 1][tx];
+      const cx<T> xz_ip = X[2][ty][tx + 1], xy_ip = X[1][ty][tx + 1];
+      hx = cur_nu[0] * (xz_jp - xo[2] - sn.xs[1] + xo[1]);
+      hy = cur_nu[1] * (sn.xs[0] - xo[0] - xz_ip + xo[2]);
+      hz = cur_nu[2] * (xy_ip - xo[1] - xx_jp + xo[0]);
+      H[0][ty][tx] = hx;
+      H[1][ty][tx] = hy;
+      H[2][ty][tx] = hz;
     }
     __syncthreads();
 
     // ---- E: gather C^T h onto the owned node's edges ----------------------
-    if (k >= kb) {
+    if (owner && k >= kb) {
       cx<T> y[3];
-      y[0] = hpy - hy + hz - H[2][ty][tx + 1];
-      y[1] = H[2][ty + 1][tx] - hz + hx - hpx;
-      y[2] = H[0][ty][tx + 1] - hx + hy - H[1][ty + 1][tx];
+      y[0] = hpy - hy + hz - H[2][ty - 1][tx];
+      y[1] = H[2][ty][tx - 1] - hz + hx - hpx;
+      y[2] = H[0][ty - 1][tx] - hx + hy - H[1][ty][tx - 1];
+      const cx<T>* xr = SYM ? cur_xr : xo;
 #pragma unroll
       for (int w = 0; w < 3; ++w) {
         cx<T> v;
         if (SYM) {
-          v = s0c.cf[w] * y[w] - w2 * s0c.xr[w];
+          v = cur_cf[w] * y[w] - w2 * xr[w];
         } else {
-          v = y[w] + s0c.cf[w] * s0c.xr[w];
+          v = y[w] + cur_cf[w] * xr[w];
         }
-        y[w] = ((s0c.mask >> w) & 1u) ? v : cx<T>{T(0), T(0)};
+        y[w] = ((cur_mask >> w) & 1u) ? v : cx<T>{T(0), T(0)};
       }
-      if (in0) op.consume(node_of(col0, k), y, s0c.xr, acc);
+      cx<T> xrv[3] = {xr[0], xr[1], xr[2]};
+      op.consume(col + (int64_t)k * plane, y, xrv, acc);
     }
     hpx = hx;
     hpy = hy;
 
     // ---- advance: plane k+1 into LDS, stage k+2, prefetch k+3 -------------
-    put_x(s0n, s1n);
-    s0c = s0n;
-    s1c = s1n;
-    process(k + 2, s0n, s1n);
+    advance();
+    process(k + 2);
     fetch(k + 3);
     __syncthreads();
   }
@@ -375,15 +307,16 @@ struct OpFinish {
   __device__ void operator()(const double* s) const { op.finalize(s); }
 };
 
-// Launch geometry for a grid and tile shape.
+// Launch geometry: block dims (tx, ty) in node columns including the halo
+// ring, so each block outputs (tx-2) x (ty-2) columns; zc planes per chunk.
 struct TileShape {
   int tx, ty, zc;
 };
 
 inline StencilLaunch make_launch(const GridView& g, TileShape t, double omega, bool xcd = true) {
   StencilLaunch L;
-  L.nbx = (g.nx + t.tx - 1) / t.tx;
-  L.nby = (g.ny + t.ty - 1) / t.ty;
+  L.nbx = (g.nx + t.tx - 3) / (t.tx - 2);
+  L.nby = (g.ny + t.ty - 3) / (t.ty - 2);
   L.zc = t.zc;
   L.nbz = (g.nz + t.zc - 1) / t.zc;
   L.omega = omega;
@@ -393,10 +326,10 @@ inline StencilLaunch make_launch(const GridView& g, TileShape t, double omega, b
 
 inline int launch_blocks(const StencilLaunch& L) { return L.nbx * L.nby * L.nbz; }
 
-// Tile shapes compiled into the library.  Every shape keeps a whole number of
-// 64-lane wavefronts and room for one halo node per thread.
+// Block shapes compiled into the library (whole wavefronts each).
 inline bool tile_supported(TileShape t) {
-  return t.zc >= 1 && ((t.tx == 64 && (t.ty == 4 || t.ty == 8)) || (t.tx == 32 && t.ty == 8));
+  return t.zc >= 1 && ((t.tx == 64 && t.ty == 8) || (t.tx == 48 && t.ty == 8) ||
+                       (t.tx == 32 && t.ty == 8) || (t.tx == 32 && t.ty == 16));
 }
 
 // Kernel-family name of an Op for the launch profiler.
@@ -415,12 +348,14 @@ fit_status launch_stencil(const GridView& g, TileShape t, double omega, const Op
   const StencilLaunch L = make_launch(g, t, omega);
   const dim3 grid((unsigned)launch_blocks(L));
   const int tok = prof_begin(s);
-  if (t.tx == 64 && t.ty == 4)
-    hipLaunchKernelGGL((stencil_kernel<T, 64, 4, MODE, Op>), grid, dim3(256), 0, s, g, L, op);
-  else if (t.tx == 64 && t.ty == 8)
+  if (t.tx == 64)
     hipLaunchKernelGGL((stencil_kernel<T, 64, 8, MODE, Op>), grid, dim3(512), 0, s, g, L, op);
-  else
+  else if (t.tx == 48)
+    hipLaunchKernelGGL((stencil_kernel<T, 48, 8, MODE, Op>), grid, dim3(384), 0, s, g, L, op);
+  else if (t.ty == 8)
     hipLaunchKernelGGL((stencil_kernel<T, 32, 8, MODE, Op>), grid, dim3(256), 0, s, g, L, op);
+  else
+    hipLaunchKernelGGL((stencil_kernel<T, 32, 16, MODE, Op>), grid, dim3(512), 0, s, g, L, op);
   FIT_HIP(hipGetLastError());
   prof_end(tok, s, OpName<Op>::get());
   if constexpr (Op::NRED > 0) {

@@ -23,8 +23,18 @@ std::map<std::tuple<int, int, int, int>, TunedEntry> g_tuned;  // (nx, ny, nz, d
 
 TileShape default_tile(const GridView& g, int dtype) {
   (void)dtype;
-  TileShape t{64, 4, 16};
-  const long nbx = (g.nx + t.tx - 1) / t.tx, nby = (g.ny + t.ty - 1) / t.ty;
+  // block width with the least padding of the last x-tile (ties: wider)
+  TileShape t{64, 8, 16};
+  long best = -1;
+  for (int bx : {64, 48, 32}) {
+    const long tiles = (g.nx + bx - 3) / (bx - 2);
+    const long waste = tiles * (bx - 2) - g.nx;
+    if (best < 0 || waste < best) {
+      best = waste;
+      t.tx = bx;
+    }
+  }
+  const long nbx = (g.nx + t.tx - 3) / (t.tx - 2), nby = (g.ny + t.ty - 3) / (t.ty - 2);
   const long cols = nbx * nby;
   int zc = g.nz;
   const long target = 1024;  // ~4 workgroups per CU on 256 CUs
@@ -83,7 +93,7 @@ extern "C" fit_status fit_tile_set(const fit_grid* g, int dtype, int tx, int ty,
   }
   TileShape t{tx, ty, zc};
   if (!tile_supported(t)) {
-    set_error("fit_tile_set: shape not compiled (TX,TY in {(64,4),(64,8),(32,8)}, zc >= 1)");
+    set_error("fit_tile_set: shape not compiled ((tx,ty) in {(64,8),(48,8),(32,8),(32,16)}, zc >= 1)");
     return FIT_E_INVALID;
   }
   record_tile(g->view, dtype, t, 0.0);
@@ -111,7 +121,7 @@ extern "C" fit_status fit_autotune(const fit_grid* g, int dtype, int scaling, do
   hipStream_t s = (hipStream_t)stream;
   (void)hipMemsetAsync(x, 0x3f, bytes, s);
   const int zcs[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
-  const TileShape shapes[] = {{64, 4, 0}, {64, 8, 0}, {32, 8, 0}};
+  const TileShape shapes[] = {{64, 8, 0}, {48, 8, 0}, {32, 8, 0}, {32, 16, 0}};
   TileShape best{64, 4, 16};
   double best_t = 1e300;
   fit_status st = FIT_OK;

@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 
 DEVS = parity_devices()
 OMEGA = 2 * np.pi * 13.7e9
-TILES = [(64, 4, 16), (64, 8, 3), (32, 8, 1), (64, 4, 5)]
+TILES = [(64, 8, 16), (48, 8, 3), (32, 8, 1), (32, 16, 5)]
 
 
 def _grid(name):
@@ -69,7 +69,7 @@ def test_matvec_c128_parity(name, scaling, tile):
 def test_matvec_c64_parity(name, scaling):
     dev = DEVS[name]
     g = _grid(name)
-    g.set_tile("c64", 64, 4, 7)
+    g.set_tile("c64", 48, 8, 7)
     x = rand_c(dev.n_edges, 12, np.complex64)
     y = g.matvec(OMEGA, _cuda(x), scaling=scaling).cpu().numpy().astype(np.complex128)
     ref = O.matvec(dev, OMEGA, x.astype(np.complex128), scaling=scaling)
@@ -144,7 +144,7 @@ def test_full_size_128_cubed_sampled_parity(dtype):
     nx, ny, nz = dev.nodes
     pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz)))
            for _ in range(120)]
-    pts += [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (63, 3, 15), (64, 4, 16), (65, 5, 17)]
+    pts += [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (63, 3, 15), (64, 4, 16), (65, 5, 17), (61, 5, 15), (62, 6, 16)]
     p0 = dev.ports[0]
     pts.append((p0.i, p0.j, (p0.k0 + p0.k1) // 2))
     worst = 0.0
@@ -165,4 +165,4 @@ def test_autotune_records_a_shape():
     dev = DEVS["layered_pec"]
     g = _grid("layered_pec")
     (tx, ty, zc), us = g.autotune("c128", "sym", OMEGA, reps=3)
-    assert (tx, ty) in {(64, 4), (64, 8), (32, 8)} and zc >= 1 and us > 0
+    assert (tx, ty) in {(64, 8), (48, 8), (32, 8), (32, 16)} and zc >= 1 and us > 0
