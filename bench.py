@@ -53,6 +53,80 @@ def measured_traffic(alg_bytes):
     return t.get("bytes_per_launch")
 
 
+def counter_sample(args):
+    """Short program for the HBM-counter passes: the bench's grid and tile,
+    40 COCG iterations, then a plain float64 negation of one complex128
+    vector (a copy-shaped kernel of exactly known traffic) that calibrates
+    the counters."""
+    import numpy as np
+    import torch
+
+    from paper_1705_08849_amd import devices as D
+    from paper_1705_08849_amd import fit
+
+    dev = D.plain_device_128(2)
+    omega = 2 * np.pi * D.log_uniform_frequency(2)
+    g = fit.Grid(dev)
+    if not args.no_autotune:
+        g.autotune("c128", "none", omega, reps=5)
+    src = torch.from_numpy(D.port_source(dev, 0)).to("cuda:0")
+    g.solve(omega, src, tol=1e-8, solver="cocg", max_iters=40, raise_on_error=False)
+    xr = torch.randn(dev.n_edges * 2, dtype=torch.float64, device="cuda:0")
+    yr = torch.empty_like(xr)
+    for _ in range(3):
+        torch.neg(xr, out=yr)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": xr.numel() * 8}), flush=True)
+
+
+def _counter_rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def ingest_counters(fetch_csv, write_csv, copy_bytes, commands):
+    """Turn the two rocprofv3 counter CSVs of `--counters` into the per-launch
+    HBM traffic of the fused COCG step-1 kernel, each counter scaled by what
+    it reads for the copy-shaped calibration kernel."""
+    def per_kernel(rows, counter):
+        acc = {}
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"]
+            acc.setdefault(name, []).append(float(r["Counter_Value"]))
+        return acc
+
+    def pick(acc, *keys):
+        hits = [v for k, v in acc.items() if all(s in k for s in keys)]
+        if not hits:
+            raise SystemExit(f"no dispatch of a kernel matching {keys}")
+        vals = [x for h in hits for x in h]
+        # a solver kernel launched after convergence returns at once; those
+        # dispatches move no vector data and are left out
+        top = max(vals)
+        vals = [x for x in vals if x > 0.05 * top]
+        return sum(vals) / len(vals), len(vals)
+
+    out = {"kernel": "cocg_step1_c128", "kernel_source_hash": kernel_source_hash(),
+           "commands": commands}
+    for counter, path, key in (("FETCH_SIZE", fetch_csv, "fetch"), ("WRITE_SIZE", write_csv, "write")):
+        acc = per_kernel(_counter_rows(path), counter)
+        kib, n = pick(acc, "stencil_kernel<double", "OpCocgP")
+        cal_kib, _ = pick(acc, "neg")
+        scale = (copy_bytes / 1024.0) / cal_kib
+        out[f"{key}_kib_raw"] = kib
+        out[f"{key}_dispatches"] = n
+        out[f"{key}_calibration_kib"] = cal_kib
+        out[f"{key}_scale"] = scale
+        out[f"{key}_bytes_per_launch"] = kib * 1024.0 * scale
+    out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def cpu_baseline(dev, omega, src, gpu_iters):
     """The FP64 oracle as it stands, one thread: assemble and scale the
     system, time 5 COCG iterations, extrapolate one solve with the GPU's
@@ -96,12 +170,24 @@ def main():
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="run only the short sample profiled by the HBM-counter passes")
+    ap.add_argument("--ingest", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_BYTES"),
+                    help="write the measured per-launch traffic from two counter CSVs")
     args = ap.parse_args()
+    if args.ingest:
+        cmds = ["rocprofv3 --pmc FETCH_SIZE -f csv -- python3 bench.py --counters",
+                "rocprofv3 --pmc WRITE_SIZE -f csv -- python3 bench.py --counters"]
+        ingest_counters(args.ingest[0], args.ingest[1], int(args.ingest[2]), cmds)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "frequency points shard across GPUs with no exchange, but nothing here "
               "launches on more than one device.", file=sys.stderr)
         sys.exit(2)
+    if args.counters:
+        counter_sample(args)
+        return
 
     import numpy as np
     import torch
