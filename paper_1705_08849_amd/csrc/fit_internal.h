@@ -227,6 +227,30 @@ __device__ __forceinline__ ColGeo<T> col_geo(const GridView& g, int i, int j) {
 }
 
 // Ids of the 2x2 cells (i-1..i, j-1..j) in plane p, packed c00|c10<<8|c01<<16|c11<<24.
+// The same four ids as two undecoded 16-bit halves (x-pairs at y-1 and y),
+// so a prefetch can be issued now and decoded a pipeline step later without
+// an early wait on the load.
+struct CellIdsRaw {
+  uint32_t lo, hi;
+};
+__device__ __forceinline__ CellIdsRaw load_cell_ids_raw(const GridView& g, int i, int j, int p) {
+  CellIdsRaw r{0xFFFFu, 0xFFFFu};
+  if (i < 0 || j < 0 || i >= g.nx || j >= g.ny || p > g.ncz || p < -1) return r;
+  const uint8_t* base = g.cell + g.cell_index(i - 1, j - 1, p);
+  r.lo = (uint32_t)base[0] | ((uint32_t)base[1] << 8);
+  r.hi = (uint32_t)base[g.ncx + 2] | ((uint32_t)base[g.ncx + 3] << 8);
+  return r;
+}
+// For 0 <= i < nx, 0 <= j < ny, -1 <= p <= ncz only (no range test, no branch).
+__device__ __forceinline__ CellIdsRaw load_cell_ids_raw_inrange(const GridView& g, int i, int j, int p) {
+  const uint8_t* base = g.cell + g.cell_index(i - 1, j - 1, p);
+  CellIdsRaw r;
+  r.lo = (uint32_t)base[0] | ((uint32_t)base[1] << 8);
+  r.hi = (uint32_t)base[g.ncx + 2] | ((uint32_t)base[g.ncx + 3] << 8);
+  return r;
+}
+__device__ __forceinline__ uint32_t decode_cell_ids(const CellIdsRaw& r) { return r.lo | (r.hi << 16); }
+
 __device__ __forceinline__ uint32_t load_cell_ids(const GridView& g, int i, int j, int p) {
   if (i < 0 || j < 0 || i >= g.nx || j >= g.ny || p > g.ncz || p < -1)
     return 0xFFFFFFFFu;  // outside the padded grid: all ghost

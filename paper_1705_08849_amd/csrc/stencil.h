@@ -108,6 +108,13 @@ __device__ __forceinline__ ZGeo<T> zgeo(const GridView& g, int p) {
   return z;
 }
 
+// The same values for an in-range plane 0 <= p < nz, loaded without a branch.
+template <class T>
+__device__ __forceinline__ ZGeo<T> zgeo_raw(const GridView& g, int p) {
+  const GeoArrays<T>& a = g.geo<T>();
+  return ZGeo<T>{a.hhz[p], a.hhz[p + 1], a.ivz[p]};
+}
+
 // Result of staging one node: the masked input, the staged (scaled) input,
 // the diagonal or scaling coefficients and the facet reluctances.
 template <class T>
@@ -189,7 +196,10 @@ __global__ void __launch_bounds__(BX* BY)
   const bool facets = tx <= TX && ty <= TY;               // tile + low halo ring
   const bool owner = tx >= 1 && tx <= TX && ty >= 1 && ty <= TY && inb;  // outputs
   const int ic = max(i, 0), jc = max(j, 0);
-  const int64_t col = (int64_t)jc * g.nx + ic;
+  // loads use the nearest in-grid column (results of out-of-grid columns are
+  // discarded), so the prefetch needs no branch
+  const int il = min(ic, g.nx - 1), jl = min(jc, g.ny - 1);
+  const int64_t col = (int64_t)jl * g.nx + il;
   const int64_t plane = (int64_t)g.nx * g.ny;
 
   fill_mat_mode<T>(mat, g.mats, L.omega, MODE);
@@ -200,25 +210,43 @@ __global__ void __launch_bounds__(BX* BY)
 
   PlaneRec<T> lo = plane_rec(mat, cg, inb ? load_cell_ids(g, i, j, ks - 1) : 0xFFFFFFFFu);
 
-  typename Op::Raw raw;
-  uint32_t ids = 0xFFFFFFFFu;
+  // Prefetch pipeline.  fetch(q) loads plane q's vector data, cell ids and
+  // z-geometry into one of two buffers; process(q) consumes that buffer one
+  // step later.  The buffers alternate (the loop below is unrolled by two),
+  // so every load lands in registers that stay put until it is consumed: no
+  // register copy -- and hence no wait on the vector memory counter, which
+  // would also drain the prefetch behind it -- happens in between.
+  struct Pending {
+    typename Op::Raw raw;
+    CellIdsRaw ids;
+    ZGeo<T> z;
+  };
+  Pending pa, pb;
   Staged<T> sn;  // the next plane (staged one step ahead)
   // the current plane: coefficients and reluctances (its staged values are in LDS)
   cx<T> cur_cf[3], cur_xr[3];
   T cur_nu[3];
   uint32_t cur_mask = 0;
 
-  auto fetch = [&](int q) {
-    if (inb && q < g.nz && q <= ke) op.load(col + (int64_t)q * plane, raw); else op.zero(raw);
-    ids = (inb && q < g.nz) ? load_cell_ids(g, i, j, q) : 0xFFFFFFFFu;
+  // Loads are unconditional, from a plane clamped into [0, min(ke, nz-1)];
+  // process() applies the validity of the plane it stages.
+  const int qmax = min(ke, g.nz - 1);
+  auto fetch = [&](int q, Pending& f) {
+    const int qc = min(q, qmax);
+    op.load(col + (int64_t)qc * plane, f.raw);
+    f.ids = load_cell_ids_raw_inrange(g, il, jl, qc);
+    f.z = zgeo_raw<T>(g, qc);
   };
-  auto process = [&](int q) {
-    const ZGeo<T> z = zgeo<T>(g, q);
-    const PlaneRec<T> hi = plane_rec(mat, cg, ids);
+  auto process = [&](int q, Pending& f) {
+    // planes above the chunk's last needed plane (or the grid) stage as ghosts
+    const bool pin = q <= qmax;
+    if (!(inb && pin)) op.zero(f.raw);
+    const ZGeo<T> z = pin ? f.z : ZGeo<T>{T(0), T(0), T(0)};
+    const PlaneRec<T> hi = plane_rec(mat, cg, (inb && pin) ? decode_cell_ids(f.ids) : 0xFFFFFFFFu);
     const NodeCoef<T> nc = node_coef(cg, lo, hi, z.hzl, z.hzh, z.ivz, q, pcoef);
     lo = hi;
     cx<T> xin[3];
-    op.input(raw, xin);
+    op.input(f.raw, xin);
     stage_node<T, MODE>(sn, xin, nc);
     if (owner && q >= kb && q < ke) op.own_input(col + (int64_t)q * plane, sn.xr);
   };
@@ -234,12 +262,12 @@ __global__ void __launch_bounds__(BX* BY)
   };
 
   // ---- prologue: stage planes ks and ks+1, prefetch ks+2 -----------------
-  fetch(ks);
-  process(ks);
+  fetch(ks, pa);
+  process(ks, pa);
   advance();
-  fetch(ks + 1);
-  process(ks + 1);
-  fetch(ks + 2);
+  fetch(ks + 1, pb);
+  process(ks + 1, pb);
+  fetch(ks + 2, pa);
   __syncthreads();
 
   double acc[NR];
@@ -247,7 +275,9 @@ __global__ void __launch_bounds__(BX* BY)
   for (int q = 0; q < NR; ++q) acc[q] = 0.0;
   cx<T> hpx = {T(0), T(0)}, hpy = {T(0), T(0)};  // own facets of the plane below
 
-  for (int k = ks; k < ke; ++k) {
+  // One plane step: facets of plane k, gather onto its edges, then stage
+  // plane k+2 from `use` and prefetch plane k+3 into `next`.
+  auto step = [&](int k, Pending& use, Pending& next) {
     // ---- C: facets of plane k (tile + low halo ring) ----------------------
     cx<T> xo[3];
     cx<T> hx = {T(0), T(0)}, hy = {T(0), T(0)}, hz = {T(0), T(0)};
@@ -290,10 +320,17 @@ __global__ void __launch_bounds__(BX* BY)
 
     // ---- advance: plane k+1 into LDS, stage k+2, prefetch k+3 -------------
     advance();
-    process(k + 2);
-    fetch(k + 3);
+    process(k + 2, use);
+    fetch(k + 3, next);
     __syncthreads();
+  };
+
+  int k = ks;
+  for (; k + 1 < ke; k += 2) {
+    step(k, pa, pb);
+    step(k + 1, pb, pa);
   }
+  if (k < ke) step(k, pa, pb);
 
   if (Op::NRED > 0) block_partial<NR>(acc, op.partials(), red_lds);
 }
