@@ -185,10 +185,14 @@ fit_status fit_material_diag(const struct fit_grid *g, int kind, double *out_dev
 fit_status fit_matvec(const struct fit_grid *g, double omega, int dtype, int scaling,
                       const void *x_dev, void *y_dev, void *stream);
 
-/* Batched operator: for b in [0, nbatch), y_b = A(omegas[b]) x_b, with the
- * nbatch vectors stored back to back (x_dev + b*n_e elements).  omegas is a
- * host array.  Reads the grid's materials once per tile for all systems.
- * Asynchronous on `stream`; 1 <= nbatch <= 64. */
+/* Batched operator (Sec. II: one system per frequency): for b in
+ * [0, nbatch), y_b = A(omegas[b]) x_b (or S_b A S_b x_b), with the nbatch
+ * vectors stored back to back (x_dev + b*n_e complex elements, same for
+ * y_dev).  omegas is a host array read before return.  Up to 16 systems
+ * share one launch, so small grids still fill the GPU.  The x and y ranges
+ * must not overlap.  Asynchronous on `stream`; 1 <= nbatch <= 64.
+ * Errors: FIT_E_INVALID (NULL, nbatch out of range, omega < 0 or not finite,
+ * SYM with omega == 0, overlap, unknown dtype or scaling). */
 fit_status fit_matvec_batched(const struct fit_grid *g, int nbatch, const double *omegas,
                               int dtype, int scaling, const void *x_dev, void *y_dev,
                               void *stream);
@@ -206,20 +210,35 @@ fit_status fit_solve(struct fit_grid *g, double omega, const void *source_dev, d
                      const fit_solve_opts *opts, void *x_dev, fit_solve_info *info);
 
 /* Frequency and right-hand-side sweep over several grids (Sec. II: each
- * frequency is an independent system; Sec. IV: multi-port excitation).
- * For every grid g, omega index f and right-hand side r, solves
- * A_g(omegas[f]) e = -j omegas[f] j_{g,r} with all systems advanced together
- * in batched launches replayed from captured hipGraphs, complex64 inner
- * iterations and complex128 refinement (opts->precision is honoured).
- *   sources_dev[g]: nrhs * n_e(g) complex128 device buffer (rhs r at r*n_e).
- *   port_v_host:    [g][f][r][p] complex128 (2 doubles) port voltages, the sum
- *                   of edge voltages over port p of grid g (Sec. IV probes);
- *                   p runs over that grid's nports, so the block of grid g has
- *                   nomega*nrhs*nports(g) entries, grids back to back.
+ * frequency and excitation is an independent system; Sec. IV: multi-port
+ * excitation).  For every grid g, omega index f and right-hand side r, solves
+ * A_g(omegas[f]) e = -j omegas[f] j_{g,r} to the true relative residual tol.
+ * Systems are advanced together in batches (up to 64 per batch, within half
+ * of the free device memory): each iteration of a batch is one operator
+ * launch over all its systems' tiles, one streaming update launch and two
+ * small finish launches, replayed from a captured hipGraph; converged
+ * systems drop out at once.  The method is the mass-preconditioned COCG of
+ * fit_solve (opts->solver must be FIT_COCG, else FIT_E_UNSUPPORTED);
+ * opts->precision FIT_PREC_FP64 iterates in complex128, FIT_PREC_MIXED in
+ * complex64 with complex128 refinement and a complex128 finish for systems
+ * whose complex64 refinement stalls.  opts->max_iters, check_every,
+ * inner_tol, use_graph and stream are honoured; scaling, restart, precond
+ * and the residual history are ignored.
+ *   omegas:         nomega host values, each finite and > 0.
+ *   sources_dev[g]: nrhs * n_e(g) complex128 device buffer (rhs r at r*n_e);
+ *                   zero on masked edges (else FIT_E_INVALID, nothing solved).
+ *   port_v_host:    NULL or [g][f][r][p] complex128 (2 doubles) port voltages,
+ *                   the sum of edge voltages over port p of grid g (Sec. IV
+ *                   probes); p runs over that grid's nports, so the block of
+ *                   grid g has nomega*nrhs*nports(g) entries, grids back to
+ *                   back.
  *   x_dev_opt:      NULL, or per grid a nomega*nrhs*n_e complex128 buffer for
- *                   the fields.
- *   infos:          ngrids*nomega*nrhs entries, or NULL.
- * Synchronous.  Returns FIT_OK only if every system met tol. */
+ *                   the fields (system (f, r) at (f*nrhs + r)*n_e).
+ *   infos:          NULL or ngrids*nomega*nrhs entries in the same order;
+ *                   time_ms is the whole sweep's wall time.
+ * All grids must live on one device.  Synchronous.  Returns FIT_OK only if
+ * every system met tol, else the first failing system's status (every
+ * system still gets its best iterate and its info). */
 fit_status fit_sweep(struct fit_grid *const *grids, int ngrids, const double *omegas, int nomega,
                      const void *const *sources_dev, int nrhs, double tol,
                      const fit_solve_opts *opts, double *port_v_host, void *const *x_dev_opt,

@@ -10,15 +10,6 @@ static fit_status unsupported(const char* name) {
   return FIT_E_UNSUPPORTED;
 }
 
-extern "C" fit_status fit_matvec_batched(const fit_grid*, int, const double*, int, int, const void*,
-                                         void*, void*) {
-  return unsupported("fit_matvec_batched");
-}
-extern "C" fit_status fit_sweep(fit_grid* const*, int, const double*, int, const void* const*, int,
-                                double, const fit_solve_opts*, double*, void* const*,
-                                fit_solve_info*) {
-  return unsupported("fit_sweep");
-}
 extern "C" fit_status fit_precond_train(fit_grid* const*, int, const double*, int,
                                         const fit_precond_cfg*, fit_precond**) {
   return unsupported("fit_precond_train");

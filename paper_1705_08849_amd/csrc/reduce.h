@@ -58,6 +58,17 @@ __device__ __forceinline__ void block_partial(double (&v)[N], double* partials, 
   }
 }
 
+// Store this block's partial sums at partials[bid * N + q].
+template <int N>
+__device__ __forceinline__ void block_partial_at(double (&v)[N], double* partials, double* lds,
+                                                 int64_t bid) {
+  block_reduce<N>(v, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) partials[bid * N + q] = v[q];
+  }
+}
+
 // Finish kernel: one block sums nblk partials in block order and hands the
 // totals to f (thread 0).  F provides skip() (nothing was reduced) and
 // operator()(const double* sums).
@@ -74,6 +85,29 @@ __global__ void __launch_bounds__(256) finish_kernel(const double* partials, int
   }
   block_reduce<N>(s, lds);
   if (threadIdx.x == 0) f(s);
+}
+
+// Several finishes in one launch: block s sums items[s]'s partials.
+template <class F>
+struct FinishItem {
+  const double* partials;
+  int nblk;
+  F f;
+};
+template <int N, class F>
+__global__ void __launch_bounds__(256) finish_multi_kernel(const FinishItem<F>* items) {
+  __shared__ double lds[N * 4];
+  const FinishItem<F>& it = items[blockIdx.x];
+  if (it.f.skip()) return;
+  double s[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) s[q] = 0.0;
+  for (int b = threadIdx.x; b < it.nblk; b += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) s[q] += it.partials[(int64_t)b * N + q];
+  }
+  block_reduce<N>(s, lds);
+  if (threadIdx.x == 0) it.f(s);
 }
 
 template <int N, class F>

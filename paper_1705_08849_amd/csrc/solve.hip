@@ -12,619 +12,13 @@
 #include "fit_internal.h"
 #include "krylov.h"
 #include "precond.h"
+#include "solver_ctx.h"
+#include "solver_kernels.h"
 #include "stencil.h"
 #include "tuning.h"
 
 namespace fit {
 
-// ---------------------------------------------------------------------------
-// Node-wise transforms that need the per-edge coefficients (mask, scaling).
-// ---------------------------------------------------------------------------
-enum XformKind { XF_RHS = 0, XF_SCALE = 1, XF_AXPY = 2, XF_SHADOW = 3 };
-
-// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator: the
-// output for counter c is the mix of seed + (c+1) * gamma.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t counter, uint64_t seed) {
-  uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-constexpr uint64_t kShadowSeed = 0x5EED;
-
-// Uniform [-1, 1) from the top 53 bits.
-__device__ __forceinline__ double u11(uint64_t h) {
-  return 2.0 * ((double)(h >> 11) * 0x1.0p-53) - 1.0;
-}
-
-template <class TI, class TO, int KIND>
-__global__ void __launch_bounds__(256)
-    node_xform_kernel(GridView g, double omega, int sym, int inverse, const TI* in, TO* out,
-                      double factor, RedOut* red, double* part, unsigned* cnt) {
-  __shared__ MatLds<double> mat;
-  __shared__ double lds[4];
-  fill_mat_mode<double>(mat, g.mats, omega, MODE_MEC);
-  __syncthreads();
-  double acc[1] = {0.0};
-  int bad = 0;
-  const cx<double> pc = port_coef_mode<double>(omega, MODE_MEC);
-  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.np;
-       n += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(n % g.nx);
-    const int j = (int)((n / g.nx) % g.ny);
-    const int p = (int)(n / ((int64_t)g.nx * g.ny));
-    const ColGeo<double> cg = col_geo<double>(g, i, j);
-    const PlaneRec<double> lo = plane_rec(mat, cg, load_cell_ids(g, i, j, p - 1));
-    const PlaneRec<double> hi = plane_rec(mat, cg, load_cell_ids(g, i, j, p));
-    const ZGeo<double> z = zgeo<double>(g, p);
-    const NodeCoef<double> nc = node_coef(cg, lo, hi, z.hzl, z.hzh, z.ivz, p, pc);
-#pragma unroll
-    for (int w = 0; w < 3; ++w) {
-      const int64_t e = 3 * n + w;
-      const bool fr = (nc.mask >> w) & 1u;
-      const cx<TI> vi = ldc(in, e);
-      const cx<double> v{(double)vi.re, (double)vi.im};
-      if (KIND == XF_SHADOW) {
-        // dense pseudo-random BiCGStab shadow vector on the free edges
-        const double re = u11(splitmix64(2ull * (uint64_t)e, kShadowSeed));
-        const double im = u11(splitmix64(2ull * (uint64_t)e + 1ull, kShadowSeed));
-        const cx<double> sv = fr ? cx<double>{re, im} : cx<double>{0.0, 0.0};
-        stc(out, e, cx<TO>{(TO)sv.re, (TO)sv.im});
-        acc[0] += cabs2(sv);
-        (void)v;
-      } else if (KIND == XF_RHS) {
-        // b = -j omega j
-        const cx<double> b = fr ? cx<double>{omega * v.im, -omega * v.re} : cx<double>{0.0, 0.0};
-        if (!fr && (v.re != 0.0 || v.im != 0.0)) bad = 1;
-        stc(out, e, cx<TO>{(TO)b.re, (TO)b.im});
-        acc[0] += cabs2(b);
-      } else {
-        cx<double> s{1.0, 0.0};
-        if (sym && fr) {
-          s = crsqrt(nc.e[w]);
-          if (inverse) {
-            const double a2 = cabs2(s);
-            s = cx<double>{s.re / a2, -s.im / a2};
-          }
-        }
-        cx<double> r = fr ? factor * (s * v) : cx<double>{0.0, 0.0};
-        if (KIND == XF_AXPY) {
-          const cx<TO> o = ldc(out, e);
-          r = cx<double>{r.re + (double)o.re, r.im + (double)o.im};
-          if (!fr) r = cx<double>{0.0, 0.0};
-        }
-        stc(out, e, cx<TO>{(TO)r.re, (TO)r.im});
-        acc[0] += cabs2(r);
-      }
-    }
-  }
-  if (red) {
-    if (bad) atomicOr(&red->flag, 1);
-    block_partial<1>(acc, part, lds);
-  }
-  (void)cnt;
-}
-
-// Stores grid-wide sums into a RedOut.
-template <int N>
-struct StoreSums {
-  RedOut* out;
-  __device__ bool skip() const { return false; }
-  __device__ void operator()(const double* s) const {
-    for (int q = 0; q < N; ++q) out->v[q] = s[q];
-  }
-};
-
-// ---------------------------------------------------------------------------
-// Element-wise vector kernels.
-// ---------------------------------------------------------------------------
-template <class T>
-__global__ void __launch_bounds__(256) zero_kernel(T* v, int64_t n2) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2;
-       e += (int64_t)gridDim.x * blockDim.x)
-    v[e] = T(0);
-}
-
-template <class T>
-__global__ void __launch_bounds__(256) copy_kernel(const T* a, T* b, int64_t n2) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2;
-       e += (int64_t)gridDim.x * blockDim.x)
-    b[e] = a[e];
-}
-
-// BiCGStab step 3: x += alpha p + omega s, r = s - omega t, <r_hat, r>, ||r||^2,
-// then the next beta and the termination tests.
-template <class T>
-__global__ void __launch_bounds__(256)
-    bicg_update_kernel(T* x, T* r, const T* p, const T* s, const T* t, const T* rh, int64_t n,
-                       BiState* st, double* part, unsigned* cnt) {
-  __shared__ double lds[3 * 4];
-  if (*(volatile int*)&st->done != kRunning) return;
-  const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
-  const cx<T> om{(T)st->omega.re, (T)st->omega.im};
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const cx<T> sv = ldc(s, e);
-    const cx<T> xv = ldc(x, e) + al * ldc(p, e) + om * sv;
-    const cx<T> rv = sv - om * ldc(t, e);
-    stc(x, e, xv);
-    stc(r, e, rv);
-    const cx<double> d = cdotc_d(ldc(rh, e), rv);
-    acc[0] += d.re;
-    acc[1] += d.im;
-    acc[2] += cabs2_d(rv);
-  }
-  block_partial<3>(acc, part, lds);
-  (void)cnt;
-}
-
-// Scalar step after the BiCGStab update's reduction: next beta and rho and
-// the termination tests.
-struct BicgFinish {
-  BiState* st;
-  __device__ bool skip() const { return *(volatile int*)&st->done != kRunning; }
-  __device__ void operator()(const double* sum) const {
-    const cx<double> rho_new{sum[0], sum[1]};
-    const double rr = sum[2];
-    st->iter += 1;
-    if (st->hist && st->iter <= st->hist_len) st->hist[st->iter - 1] = sqrt(rr) * st->hscale;
-    if (!isfinite(rr) || !isfinite(sum[0]) || !isfinite(sum[1])) {
-      st->done = kNan;
-      return;
-    }
-    // beta = (rho_new / rho) * (alpha / omega)
-    const cx<double> rho = st->rho, a = st->alpha, w = st->omega;
-    const double r2 = cabs2(rho), w2 = cabs2(w);
-    st->rr = rr;
-    if (rr <= st->tol2) {
-      st->done = kConverged;
-      st->rho = rho_new;
-      return;
-    }
-    // <r_hat, r> negligible against |r_hat| |r| at the working precision:
-    // the shadow space has collapsed (restart)
-    if (r2 == 0.0 || w2 == 0.0 || cabs2(rho_new) < 1e-28 * rr * st->rhrh) {
-      st->reason = (r2 == 0.0 || w2 == 0.0) ? 4 : 3;
-      st->done = kBreakdown;
-      return;
-    }
-    const cx<double> q{(rho_new.re * rho.re + rho_new.im * rho.im) / r2,
-                       (rho_new.im * rho.re - rho_new.re * rho.im) / r2};
-    const cx<double> aw{(a.re * w.re + a.im * w.im) / w2, (a.im * w.re - a.re * w.im) / w2};
-    st->beta = q * aw;
-    st->rho = rho_new;
-    if (st->iter >= st->max_iter) st->done = kMaxIter;
-  }
-};
-
-// Multi-dot h_i = <V_i, w>, i < nv: each block keeps its chunk of w in
-// registers and walks the basis vectors; partials[i * nblk + blk].
-constexpr int kMdPer = 4;  // complex elements per thread
-template <class T>
-__global__ void __launch_bounds__(256)
-    multidot_kernel(const T* V, int64_t ldv, int nv, const T* w, int64_t n, double* part,
-                    const GmState* st) {
-  __shared__ double lds[2 * 4];
-  if (st && *(volatile const int*)&st->done != kRunning) return;
-  const int64_t base = (int64_t)blockIdx.x * 256 * kMdPer;
-  cx<T> wl[kMdPer];
-#pragma unroll
-  for (int q = 0; q < kMdPer; ++q) {
-    const int64_t e = base + q * 256 + threadIdx.x;
-    wl[q] = e < n ? ldc(w, e) : cx<T>{T(0), T(0)};
-  }
-  for (int i = 0; i < nv; ++i) {
-    double acc[2] = {0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < kMdPer; ++q) {
-      const int64_t e = base + q * 256 + threadIdx.x;
-      if (e < n) {
-        const cx<double> d = cdotc_d(ldc(V + 2 * ldv * i, e), wl[q]);
-        acc[0] += d.re;
-        acc[1] += d.im;
-      }
-    }
-    block_reduce<2>(acc, lds);
-    if (threadIdx.x == 0) {
-      part[2 * ((int64_t)i * gridDim.x + blockIdx.x)] = acc[0];
-      part[2 * ((int64_t)i * gridDim.x + blockIdx.x) + 1] = acc[1];
-    }
-  }
-}
-
-// Sum the multi-dot partials: one block per basis vector, fixed order.
-__global__ void __launch_bounds__(256)
-    multidot_finish_kernel(const double* part, int nblk, GmState* st, int accumulate) {
-  __shared__ double lds[2 * 4];
-  if (*(volatile int*)&st->done != kRunning) return;
-  const int i = blockIdx.x;
-  double acc[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    acc[0] += part[2 * ((int64_t)i * nblk + b)];
-    acc[1] += part[2 * ((int64_t)i * nblk + b) + 1];
-  }
-  block_reduce<2>(acc, lds);
-  if (threadIdx.x == 0) {
-    st->hcol[i] = cx<double>{acc[0], acc[1]};
-    const int ld = st->m + 1;
-    cx<double>& h = st->h[(int64_t)st->j * ld + i];
-    h = accumulate ? h + st->hcol[i] : st->hcol[i];
-  }
-}
-
-// w -= sum_i hcol_i V_i; optionally ||w||^2 into `out`.
-template <class T>
-__global__ void __launch_bounds__(256)
-    multi_axpy_kernel(const T* V, int64_t ldv, int nv, T* w, int64_t n, GmState* st,
-                      RedOut* out, double* part, unsigned* cnt) {
-  __shared__ double lds[4];
-  __shared__ cx<double> hc[kMaxRestart + 1];
-  if (*(volatile int*)&st->done != kRunning) return;
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) hc[i] = st->hcol[i];
-  __syncthreads();
-  double acc[1] = {0.0};
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    cx<T> v = ldc(w, e);
-    for (int i = 0; i < nv; ++i) {
-      const cx<T> h{(T)hc[i].re, (T)hc[i].im};
-      v = v - h * ldc(V + 2 * ldv * i, e);
-    }
-    stc(w, e, v);
-    acc[0] += cabs2_d(v);
-  }
-  if (out) block_partial<1>(acc, part, lds);
-  (void)cnt;
-}
-
-// Completes Arnoldi step j: h_{j+1,j} = ||w||, applies the previous Givens
-// rotations to column j, forms the new one, updates g and tests convergence.
-__global__ void gmres_step_kernel(GmState* st, const RedOut* wn) {
-  if (threadIdx.x != 0 || st->done != kRunning) return;
-  const int m = st->m, ld = m + 1, j = st->j;
-  cx<double>* h = st->h + (int64_t)j * ld;
-  const double hn = sqrt(wn->v[0]);
-  h[j + 1] = cx<double>{hn, 0.0};
-  for (int i = 0; i < j; ++i) {
-    const cx<double> c = st->cs[i], s = st->sn[i];
-    const cx<double> a = h[i], b = h[i + 1];
-    // [conj(c) conj(s); -s c] applied to (a, b)
-    h[i] = cx<double>{c.re * a.re + c.im * a.im + s.re * b.re + s.im * b.im,
-                      c.re * a.im - c.im * a.re + s.re * b.im - s.im * b.re};
-    h[i + 1] = cx<double>{-(s.re * a.re - s.im * a.im) + (c.re * b.re - c.im * b.im),
-                          -(s.re * a.im + s.im * a.re) + (c.re * b.im + c.im * b.re)};
-  }
-  const cx<double> a = h[j], b = h[j + 1];
-  const double rho = sqrt(cabs2(a) + cabs2(b));
-  cx<double> c{1.0, 0.0}, s{0.0, 0.0};
-  if (rho > 0.0) {
-    c = cx<double>{a.re / rho, a.im / rho};
-    s = cx<double>{b.re / rho, b.im / rho};
-  }
-  st->cs[j] = c;
-  st->sn[j] = s;
-  h[j] = cx<double>{rho, 0.0};
-  h[j + 1] = cx<double>{0.0, 0.0};
-  const cx<double> gj = st->g[j];
-  st->g[j + 1] = cx<double>{-(s.re * gj.re - s.im * gj.im), -(s.re * gj.im + s.im * gj.re)};
-  st->g[j] = cx<double>{c.re * gj.re + c.im * gj.im, c.re * gj.im - c.im * gj.re};
-  st->iter += 1;
-  const double res = sqrt(cabs2(st->g[j + 1]));
-  if (st->hist && st->iter <= st->hist_len) st->hist[st->iter - 1] = res * st->hscale;
-  st->k = j + 1;
-  st->vscale = hn > 0.0 ? 1.0 / hn : 0.0;
-  st->j = j + 1;
-  if (!isfinite(res) || !isfinite(hn)) {
-    st->done = kNan;
-  } else if (res <= st->tol) {
-    st->done = kConverged;
-  } else if (hn == 0.0) {
-    st->done = kConverged;  // lucky breakdown: the Krylov space is invariant
-  } else if (st->iter >= st->max_iter) {
-    st->done = kMaxIter;
-  } else if (st->j >= m) {
-    st->done = kBreakdown;  // cycle complete: restart (not a failure)
-  }
-}
-
-// Back substitution of the k x k upper-triangular least-squares system.
-__global__ void gmres_solve_kernel(GmState* st) {
-  if (threadIdx.x != 0) return;
-  const int k = st->k, ld = st->m + 1;
-  for (int i = k - 1; i >= 0; --i) {
-    cx<double> v = st->g[i];
-    for (int q = i + 1; q < k; ++q) v = v - st->h[(int64_t)q * ld + i] * st->y[q];
-    const cx<double> d = st->h[(int64_t)i * ld + i];
-    const double d2 = cabs2(d);
-    st->y[i] = d2 > 0 ? cx<double>{(v.re * d.re + v.im * d.im) / d2, (v.im * d.re - v.re * d.im) / d2}
-                      : cx<double>{0.0, 0.0};
-  }
-}
-
-// x += sum_i y_i B_i (B = V for GMRES, Z for FGMRES).
-template <class T>
-__global__ void __launch_bounds__(256)
-    gmres_update_kernel(T* x, const T* B, int64_t ldb, int64_t n, const GmState* st) {
-  __shared__ cx<double> yl[kMaxRestart];
-  const int k = st->k;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) yl[i] = st->y[i];
-  __syncthreads();
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    cx<T> v = ldc(x, e);
-    for (int i = 0; i < k; ++i) v = v + cx<T>{(T)yl[i].re, (T)yl[i].im} * ldc(B + 2 * ldb * i, e);
-    stc(x, e, v);
-  }
-}
-
-// COCG step 2: x += alpha p, r -= alpha q, r^T r, ||r||^2, next beta and the
-// termination tests.
-template <class T>
-__global__ void __launch_bounds__(256)
-    cocg_update_kernel(T* x, T* r, const T* p, const T* q, int64_t n, CgState* st, double* part,
-                       unsigned* cnt) {
-  __shared__ double lds[3 * 4];
-  if (*(volatile int*)&st->done != kRunning) return;
-  const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const cx<T> xv = ldc(x, e) + al * ldc(p, e);
-    const cx<T> rv = ldc(r, e) - al * ldc(q, e);
-    stc(x, e, xv);
-    stc(r, e, rv);
-    const double rr = rv.re, ri = rv.im;
-    acc[0] += rr * rr - ri * ri;
-    acc[1] += 2.0 * rr * ri;
-    acc[2] += rr * rr + ri * ri;
-  }
-  block_partial<3>(acc, part, lds);
-  (void)cnt;
-}
-
-// Scalar step after the COCG update's reduction.
-struct CocgFinish {
-  CgState* st;
-  __device__ bool skip() const { return *(volatile int*)&st->done != kRunning; }
-  __device__ void operator()(const double* sum) const {
-    const cx<double> rho_new{sum[0], sum[1]};
-    const double rr = sum[2];
-    st->iter += 1;
-    if (st->hist && st->iter <= st->hist_len) st->hist[st->iter - 1] = sqrt(rr) * st->hscale;
-    if (!isfinite(rr) || !isfinite(sum[0]) || !isfinite(sum[1])) {
-      st->done = kNan;
-      return;
-    }
-    st->rr = rr;
-    if (rr <= st->tol2) {
-      st->done = kConverged;
-      return;
-    }
-    const cx<double> rho = st->rho;
-    const double r2 = cabs2(rho);
-    if (r2 == 0.0 || cabs2(rho_new) < 1e-28 * rr * rr) {
-      st->reason = 3;  // r^T r vanishes: r is (nearly) a quasi-null vector
-      st->done = kBreakdown;
-      return;
-    }
-    st->beta = cx<double>{(rho_new.re * rho.re + rho_new.im * rho.im) / r2,
-                          (rho_new.im * rho.re - rho_new.re * rho.im) / r2};
-    st->rho = rho_new;
-    if (st->iter >= st->max_iter) st->done = kMaxIter;
-  }
-};
-
-// The diagonal preconditioner of the mass-preconditioned COCG:
-// m = 1/M_eps,c per free edge (0 on masked edges) -- the square of the
-// symmetric scaling S, from the same per-edge rule as the operator.
-template <class T>
-__global__ void __launch_bounds__(256)
-    mass_inverse_kernel(GridView g, double omega, T* m_out) {
-  __shared__ MatLds<double> mat;
-  fill_mat_mode<double>(mat, g.mats, omega, MODE_MEC);
-  const cx<double> pc = port_coef_mode<double>(omega, MODE_MEC);
-  __syncthreads();
-  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.np;
-       n += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(n % g.nx);
-    const int j = (int)((n / g.nx) % g.ny);
-    const int k = (int)(n / ((int64_t)g.nx * g.ny));
-    const ColGeo<double> cg = col_geo<double>(g, i, j);
-    const PlaneRec<double> lo = plane_rec(mat, cg, load_cell_ids(g, i, j, k - 1));
-    const PlaneRec<double> hi = plane_rec(mat, cg, load_cell_ids(g, i, j, k));
-    const ZGeo<double> zg = zgeo<double>(g, k);
-    const NodeCoef<double> nc = node_coef(cg, lo, hi, zg.hzl, zg.hzh, zg.ivz, k, pc);
-#pragma unroll
-    for (int w = 0; w < 3; ++w) {
-      cx<T> mv{T(0), T(0)};
-      if ((nc.mask >> w) & 1u) {
-        const cx<double> me = nc.e[w];
-        const double m2 = cabs2(me);
-        mv = cx<T>{(T)(me.re / m2), (T)(-me.im / m2)};
-      }
-      stc(m_out, 3 * n + w, mv);
-    }
-  }
-}
-
-// Mass-preconditioned COCG step 2: x += alpha p, r -= alpha q, z = m .* r,
-// r^T z and ||r||^2.  COCG preconditioned by S^2 produces the iterates of
-// COCG on S A S while the operator itself runs unscaled.  INIT: only
-// z = m .* r and the sums.
-template <class T, bool INIT>
-__global__ void __launch_bounds__(256)
-    pcocg_update_kernel(int64_t n, T* x, T* r, T* z, const T* p, const T* q, const T* m,
-                        CgState* st, double* part) {
-  __shared__ double lds[3 * 4];
-  if (*(volatile int*)&st->done != kRunning) return;
-  const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    cx<T> rv = ldc(r, e);
-    if (!INIT) {
-      stc(x, e, ldc(x, e) + al * ldc(p, e));
-      rv = rv - al * ldc(q, e);
-      stc(r, e, rv);
-    }
-    const cx<T> zv = ldc(m, e) * rv;
-    stc(z, e, zv);
-    const double rr = rv.re, ri = rv.im, zr = zv.re, zi = zv.im;
-    acc[0] += rr * zr - ri * zi;
-    acc[1] += rr * zi + ri * zr;
-    acc[2] += rr * rr + ri * ri;
-  }
-  block_partial<3>(acc, part, lds);
-}
-
-// Initial scalars of the mass-preconditioned COCG: rho = r^T z, ||r||^2.
-struct PcocgInitFinish {
-  CgState* st;
-  __device__ bool skip() const { return false; }
-  __device__ void operator()(const double* sum) const {
-    st->rho = cx<double>{sum[0], sum[1]};
-    st->rr = sum[2];
-    st->beta = cx<double>{0.0, 0.0};
-    if (!isfinite(sum[0]) || !isfinite(sum[1]) || !isfinite(sum[2])) st->done = kNan;
-  }
-};
-
-// <a, b> (or the bilinear a^T b), ||a||^2, ||b||^2 -> out->v[0..3].
-template <class T, bool BILINEAR = false>
-__global__ void __launch_bounds__(256)
-    dot_kernel(const T* a, const T* b, int64_t n, RedOut* out, double* part, unsigned* cnt) {
-  __shared__ double lds[4 * 4];
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const cx<T> av = ldc(a, e), bv = ldc(b, e);
-    const cx<double> d = BILINEAR ? cdotc_d(cx<T>{av.re, -av.im}, bv) : cdotc_d(av, bv);
-    acc[0] += d.re;
-    acc[1] += d.im;
-    acc[2] += cabs2_d(av);
-    acc[3] += cabs2_d(bv);
-  }
-  block_partial<4>(acc, part, lds);
-  (void)cnt;
-  (void)out;
-}
-
-// v_j = w * vscale (FGMRES keeps the normalised vector for the preconditioner).
-template <class T>
-__global__ void __launch_bounds__(256)
-    gm_normalize_kernel(const T* w, T* v, int64_t n, const GmState* st) {
-  if (*(volatile const int*)&st->done != kRunning) return;
-  const T sc = (T)st->vscale;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    stc(v, e, sc * ldc(w, e));
-}
-
-// Re-arm the state after a completed cycle so the restart's operator
-// application runs.
-__global__ void gm_restart_prep_kernel(GmState* st) {
-  if (threadIdx.x == 0) st->done = kRunning;
-}
-
-// w = r0 - w, ||w||^2.
-template <class T>
-__global__ void __launch_bounds__(256)
-    sub_norm_kernel(const T* r0, T* w, int64_t n, RedOut* out, double* part, unsigned* cnt) {
-  __shared__ double lds[4];
-  double acc[1] = {0.0};
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const cx<T> v = ldc(r0, e) - ldc(w, e);
-    stc(w, e, v);
-    acc[0] += cabs2_d(v);
-  }
-  block_partial<1>(acc, part, lds);
-  (void)cnt;
-  (void)out;
-}
-
-// ---------------------------------------------------------------------------
-// Host-side solver context.
-// ---------------------------------------------------------------------------
-struct Ctx {
-  fit_grid* g;
-  hipStream_t s;
-  double omega;
-  int sym;
-  // reduction scratch
-  double* part;
-  unsigned* cnt;
-  RedOut* red;
-  BiState* bst;
-  GmState* gst;
-  RedOut* h_red;   // pinned host mirrors
-  BiState* h_bst;
-  GmState* h_gst;
-  CgState* cst = nullptr;
-  CgState* h_cst = nullptr;
-  int max_blocks;
-  double bytes = 0.0;  // algorithmic bytes launched
-  int matvecs = 0;
-  int last_reason = 0;   // breakdown test of the last inner BiCGStab
-  double last_rr = 0.0;  // its final recursive ||r||^2 (unit initial norm)
-  TileShape tile128, tile64;
-};
-
-static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-template <class T, class Op>
-static fit_status launch_op_stencil_mode(Ctx& c, bool sym, const Op& op) {
-  const TileShape t = sizeof(T) == 8 ? c.tile128 : c.tile64;
-  if (sym) return launch_stencil<T, MODE_MEC>(c.g->view, t, c.omega, op, c.s);
-  return launch_stencil<T, MODE_D>(c.g->view, t, c.omega, op, c.s);
-}
-
-static double node_bytes(const fit_grid* g, int vec_passes, size_t elem) {
-  return (double)g->view.np * 3.0 * elem * vec_passes + (double)g->view.ncx * g->view.ncy * g->view.ncz;
-}
-
-// r = b - A x (unscaled complex128), ||r||^2 -> c.red->v[0]; optional c64 copy.
-static fit_status residual(Ctx& c, const double* x, const double* b, double* r, float* r32,
-                           double r32_scale) {
-  OpResidual<double> op{x, b, r, r32, r32_scale, c.red, c.part, c.cnt};
-  c.bytes += node_bytes(c.g, 2 + (r ? 1 : 0), 16) + (r32 ? (double)c.g->ne * 8 : 0.0);
-  c.matvecs += 1;
-  return launch_op_stencil_mode<double>(c, false, op);
-}
-
-template <class TI, class TO, int KIND>
-static fit_status xform(Ctx& c, bool sym, bool inverse, const TI* in, TO* out, double factor,
-                        bool reduce) {
-  hipLaunchKernelGGL((node_xform_kernel<TI, TO, KIND>), dim3(pw_blocks(c.g->view.np)), dim3(256), 0,
-                     c.s, c.g->view, c.omega, sym ? 1 : 0, inverse ? 1 : 0, in, out, factor,
-                     reduce ? c.red : nullptr, c.part, c.cnt);
-  FIT_HIP(hipGetLastError());
-  if (reduce) FIT_HIP(launch_finish<1>(c.part, pw_blocks(c.g->view.np), StoreSums<1>{c.red}, c.s));
-  c.bytes += (double)c.g->ne * (sizeof(TI) + sizeof(TO)) * 2 * (KIND == XF_AXPY ? 1.5 : 1.0);
-  return FIT_OK;
-}
-
-template <class T>
-static fit_status vzero(Ctx& c, T* v, int64_t ncomplex) {
-  hipLaunchKernelGGL(zero_kernel<T>, dim3(pw_blocks(2 * ncomplex)), dim3(256), 0, c.s, v,
-                     2 * ncomplex);
-  FIT_HIP(hipGetLastError());
-  return FIT_OK;
-}
-template <class T>
-static fit_status vcopy(Ctx& c, const T* a, T* b, int64_t ncomplex) {
-  hipLaunchKernelGGL(copy_kernel<T>, dim3(pw_blocks(2 * ncomplex)), dim3(256), 0, c.s, a, b,
-                     2 * ncomplex);
-  FIT_HIP(hipGetLastError());
-  return FIT_OK;
-}
-
-static fit_status sync_copy(Ctx& c, void* dst, const void* src, size_t bytes) {
-  FIT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.s));
-  FIT_HIP(hipStreamSynchronize(c.s));
-  return FIT_OK;
-}
 
 // ---------------------------------------------------------------------------
 // BiCGStab on A_int x = r0 (A_int = S A S when sym), starting from x = 0.
@@ -921,59 +315,6 @@ struct IdentityPrecond : PrecondApply {
   }
 };
 
-// Bump allocator over the grid's workspace arena.
-struct Arena {
-  char* base;
-  size_t off = 0, cap;
-  template <class P>
-  P* take(size_t bytes) {
-    P* p = (P*)(base + off);
-    off += align_up(bytes, 256);
-    return p;
-  }
-};
-
-fit_status setup_ctx(Ctx& c, fit_grid* g, double omega, int sym, hipStream_t s) {
-  c.g = g;
-  c.s = s;
-  c.omega = omega;
-  c.sym = sym;
-  c.tile128 = tile_for(g, FIT_C128);
-  c.tile64 = tile_for(g, FIT_C64);
-  const int b128 = launch_blocks(make_launch(g->view, c.tile128, omega));
-  const int b64 = launch_blocks(make_launch(g->view, c.tile64, omega));
-  c.max_blocks = std::max(std::max(b128, b64), 4096);
-  const size_t need = align_up(sizeof(double) * 4 * (size_t)c.max_blocks, 256) + 256 +
-                      align_up(sizeof(RedOut), 256) + align_up(sizeof(BiState), 256) +
-                      align_up(sizeof(GmState), 256) + align_up(sizeof(CgState), 256);
-  fit_status st = ensure_ws(g->red, need, g->device);
-  if (st != FIT_OK) return st;
-  char* p = (char*)g->red.ptr;
-  c.part = (double*)p;
-  p += align_up(sizeof(double) * 4 * (size_t)c.max_blocks, 256);
-  c.cnt = (unsigned*)p;
-  p += 256;
-  c.red = (RedOut*)p;
-  p += align_up(sizeof(RedOut), 256);
-  c.bst = (BiState*)p;
-  p += align_up(sizeof(BiState), 256);
-  c.gst = (GmState*)p;
-  p += align_up(sizeof(GmState), 256);
-  c.cst = (CgState*)p;
-  if (!g->pinned) {
-    FIT_HIP(hipHostMalloc(&g->pinned, sizeof(RedOut) + sizeof(BiState) + sizeof(GmState) +
-                                          sizeof(CgState) + 256));
-  }
-  char* hp = (char*)g->pinned;
-  c.h_red = (RedOut*)hp;
-  c.h_bst = (BiState*)(hp + sizeof(RedOut));
-  c.h_gst = (GmState*)(hp + sizeof(RedOut) + sizeof(BiState));
-  c.h_cst = (CgState*)(hp + sizeof(RedOut) + sizeof(BiState) + sizeof(GmState));
-  // ticket counter starts at zero; the red block's flag too
-  FIT_HIP(hipMemsetAsync(c.cnt, 0, 256, s));
-  FIT_HIP(hipMemsetAsync(c.red, 0, sizeof(RedOut), s));
-  return FIT_OK;
-}
 
 // Inner solve in precision T on A_int d = rin (rin has unit norm), from d = 0.
 template <class T>

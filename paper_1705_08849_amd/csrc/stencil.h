@@ -162,16 +162,17 @@ __device__ __forceinline__ void stage_node(Staged<T>& st, const cx<T> (&xin)[3],
 //   double* partials() const;                       block partial sums
 //   void finalize(const double* sums) const;        scalar step (finish kernel)
 // ---------------------------------------------------------------------------
+// Body of one workgroup: logical tile lb of the launch L on grid g.  Its
+// reduction partials go to op.partials() at index lb.
 template <class T, int BX, int BY, int MODE, class Op>
-__global__ void __launch_bounds__(BX* BY)
-    stencil_kernel(GridView g, StencilLaunch L, Op op) {
+__device__ __forceinline__ void stencil_body(const GridView& g, const StencilLaunch& L, Op& op,
+                                             int lb) {
   constexpr int TX = BX - 2, TY = BY - 2;
   constexpr int NT = BX * BY;
   static_assert(NT % 64 == 0, "whole wavefronts");
   constexpr bool SYM = (MODE == MODE_MEC);
   constexpr int NR = Op::NRED > 0 ? Op::NRED : 1;
 
-  if (op.skip()) return;
   op.begin();
 
   __shared__ MatLds<T> mat;
@@ -181,7 +182,6 @@ __global__ void __launch_bounds__(BX* BY)
 
   const int tid = threadIdx.x;
   const int tx = tid % BX, ty = tid / BX;
-  const int lb = L.xcd_aware ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int bx = lb % L.nbx;
   const int rest = lb / L.nbx;
   const int by = rest % L.nby;
@@ -332,7 +332,43 @@ __global__ void __launch_bounds__(BX* BY)
   }
   if (k < ke) step(k, pa, pb);
 
-  if (Op::NRED > 0) block_partial<NR>(acc, op.partials(), red_lds);
+  if (Op::NRED > 0) block_partial_at<NR>(acc, op.partials(), red_lds, lb);
+}
+
+template <class T, int BX, int BY, int MODE, class Op>
+__global__ void __launch_bounds__(BX* BY)
+    stencil_kernel(GridView g, StencilLaunch L, Op op) {
+  if (op.skip()) return;
+  const int lb = L.xcd_aware ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  stencil_body<T, BX, BY, MODE, Op>(g, L, op, lb);
+}
+
+// Several operator applications in one launch (systems of a sweep, possibly
+// on different grids): item s owns the logical blocks [block0, block0+nblk).
+// The XCD-aware order runs over the whole launch, so a system's neighbouring
+// tiles still share an XCD.
+template <class Op>
+struct MultiItem {
+  GridView g;
+  StencilLaunch L;
+  Op op;
+  int block0, nblk;
+};
+
+template <class T, int BX, int BY, int MODE, class Op>
+__global__ void __launch_bounds__(BX* BY)
+    stencil_multi_kernel(const MultiItem<Op>* __restrict__ items, int nitems) {
+  const int gb = xcd_remap(blockIdx.x, gridDim.x);
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {  // last item whose block0 <= gb
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].block0 <= gb) lo = mid; else hi = mid - 1;
+  }
+  Op op = items[lo].op;
+  if (op.skip()) return;
+  const GridView g = items[lo].g;
+  const StencilLaunch L = items[lo].L;
+  stencil_body<T, BX, BY, MODE, Op>(g, L, op, gb - items[lo].block0);
 }
 
 // Finish functor: hands the grid-wide sums of an Op's reductions to its
@@ -401,6 +437,30 @@ fit_status launch_stencil(const GridView& g, TileShape t, double omega, const Op
   return FIT_OK;
 }
 
+// One launch over several systems' tiles (items on the device, `nblocks`
+// logical blocks in total); every item uses the block shape (tx, ty).
+template <class T, int MODE, class Op>
+fit_status launch_stencil_multi(const MultiItem<Op>* items, int nitems, int nblocks, TileShape t,
+                                hipStream_t s, const char* prof_name) {
+  if (!tile_supported(t) || nitems < 1 || nblocks < 1) {
+    set_error("unsupported batched stencil launch");
+    return FIT_E_INVALID;
+  }
+  const dim3 grid((unsigned)nblocks);
+  const int tok = prof_begin(s);
+  if (t.tx == 64)
+    hipLaunchKernelGGL((stencil_multi_kernel<T, 64, 8, MODE, Op>), grid, dim3(512), 0, s, items, nitems);
+  else if (t.tx == 48)
+    hipLaunchKernelGGL((stencil_multi_kernel<T, 48, 8, MODE, Op>), grid, dim3(384), 0, s, items, nitems);
+  else if (t.ty == 8)
+    hipLaunchKernelGGL((stencil_multi_kernel<T, 32, 8, MODE, Op>), grid, dim3(256), 0, s, items, nitems);
+  else
+    hipLaunchKernelGGL((stencil_multi_kernel<T, 32, 16, MODE, Op>), grid, dim3(512), 0, s, items, nitems);
+  FIT_HIP(hipGetLastError());
+  prof_end(tok, s, prof_name);
+  return FIT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Plain operator application: y = A x.
 // ---------------------------------------------------------------------------
@@ -439,5 +499,50 @@ template <class T>
 struct OpName<OpMatvec<T>> {
   static const char* get() { return "matvec"; }
 };
+
+// Several right-hand sides / frequencies on one grid in one launch:
+// y_b = A(omega_b) x_b for b < n (n <= kMax); gridDim.y = n.
+template <class T>
+struct BatchVecs {
+  static constexpr int kMax = 16;
+  const T* x[kMax];
+  T* y[kMax];
+  double omega[kMax];
+};
+
+template <class T, int BX, int BY, int MODE>
+__global__ void __launch_bounds__(BX* BY)
+    stencil_batch_kernel(GridView g, StencilLaunch L, BatchVecs<T> a) {
+  const int nb = (int)(gridDim.x * gridDim.y);
+  const int lin = xcd_remap((int)(blockIdx.x + blockIdx.y * gridDim.x), nb);
+  const int b = lin / (int)gridDim.x, lb = lin % (int)gridDim.x;
+  OpMatvec<T> op{a.x[b], a.y[b]};
+  StencilLaunch Lb = L;
+  Lb.omega = a.omega[b];
+  stencil_body<T, BX, BY, MODE, OpMatvec<T>>(g, Lb, op, lb);
+}
+
+template <class T, int MODE>
+fit_status launch_stencil_batch(const GridView& g, TileShape t, const BatchVecs<T>& a, int n,
+                                hipStream_t s) {
+  if (!tile_supported(t) || n < 1 || n > BatchVecs<T>::kMax) {
+    set_error("unsupported batched operator launch");
+    return FIT_E_INVALID;
+  }
+  const StencilLaunch L = make_launch(g, t, a.omega[0]);
+  const dim3 grid((unsigned)launch_blocks(L), (unsigned)n);
+  const int tok = prof_begin(s);
+  if (t.tx == 64)
+    hipLaunchKernelGGL((stencil_batch_kernel<T, 64, 8, MODE>), grid, dim3(512), 0, s, g, L, a);
+  else if (t.tx == 48)
+    hipLaunchKernelGGL((stencil_batch_kernel<T, 48, 8, MODE>), grid, dim3(384), 0, s, g, L, a);
+  else if (t.ty == 8)
+    hipLaunchKernelGGL((stencil_batch_kernel<T, 32, 8, MODE>), grid, dim3(256), 0, s, g, L, a);
+  else
+    hipLaunchKernelGGL((stencil_batch_kernel<T, 32, 16, MODE>), grid, dim3(512), 0, s, g, L, a);
+  FIT_HIP(hipGetLastError());
+  prof_end(tok, s, sizeof(T) == 8 ? "matvec_batched_c128" : "matvec_batched_c64");
+  return FIT_OK;
+}
 
 }  // namespace fit

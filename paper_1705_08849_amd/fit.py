@@ -317,7 +317,7 @@ class Grid:
 
 
 def sweep(grids: Sequence[Grid], omegas: Sequence[float], sources, tol: float = 1e-8,
-          solver: str = "bicgstab", precision: str = "mixed", scaling: str = "sym",
+          solver: str = "cocg", precision: str = "fp64", scaling: str = "sym",
           max_iters: int = 0, check_every: int = 0, inner_tol: float = 0.0, xs=None,
           restart: int = 30, stream=None):
     """``fit_sweep``: solve every (grid, omega, rhs) system.  ``sources[g]`` is

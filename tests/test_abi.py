@@ -92,4 +92,19 @@ def test_null_arguments_are_rejected():
     assert L.fit_edge_mask(None, None, None) == fit.E_INVALID
     assert L.fit_num_edges(None) == -1
     L.fit_grid_destroy(None)
-    assert L.fit_tile_set(None, 0, 64, 4, 8) == fit.E_INVALID
+    assert L.fit_tile_set(None, 0, 64, 8, 8) == fit.E_INVALID
+
+
+def test_batched_and_sweep_argument_checks():
+    """Argument validation of the batched entry points needs no device."""
+    L = fit.lib()
+    om = (C.c_double * 2)(1e9, 2e9)
+    assert L.fit_matvec_batched(None, 2, om, 0, 0, None, None, None) == fit.E_INVALID
+    assert L.fit_sweep(None, 1, om, 2, None, 1, 1e-8, None, None, None, None) == fit.E_INVALID
+    gh = (C.c_void_p * 1)(None)
+    src = (C.c_void_p * 1)(None)
+    assert L.fit_sweep(gh, 1, om, 2, src, 1, 1e-8, None, None, None, None) == fit.E_INVALID
+    assert "NULL" in fit.last_error()
+    assert L.fit_sweep(gh, 1, om, 2, src, 1, 2.0, None, None, None, None) == fit.E_INVALID
+    bad = (C.c_double * 2)(1e9, -1.0)
+    assert L.fit_sweep(gh, 1, bad, 2, src, 1, 1e-8, None, None, None, None) == fit.E_INVALID
