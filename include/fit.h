@@ -289,34 +289,77 @@ fit_status fit_profile_start(void);
  * more than max). */
 fit_status fit_profile_stop(fit_kernel_stat *out, int max, int *n);
 
-/* ---- learned right preconditioner (3-level 3D U-Net, BF16 MFMA) ---------- */
+/* ---- learned right preconditioner (3-level 3D U-Net, BF16 MFMA) ---------- *
+ *
+ * A nonlinear right preconditioner z = M(v) for FIT_FGMRES (Sec. IV: flexible
+ * GMRES stores the preconditioned directions, so M may change from one
+ * application to the next and need not be linear).  M(v) = s U(v/s) with
+ * s = rms(v) over the free edges and U a 3-level 3D U-Net over the node grid
+ * (base channels c, 2c, 4c; two 3x3x3 convolutions per level, 2x2x2 stride-2
+ * down and transposed up convolutions, skip concatenations, a 1x1x1 head,
+ * ReLU).  Input per node: Re/Im of its three edge values of v/s, eps_r/12 and
+ * (log10(sigma + 1e-3) + 3)/11 of the cell it owns, log10(f/GHz)/1.6 and
+ * log10(h/100 um) of that cell's three widths; output:
+ * Re/Im of its three edge values of z/s; masked edges give 0.  All
+ * convolutions run as BF16 MFMA implicit GEMMs with fp32 accumulation; bf16
+ * activations and weights, fp32 biases, master weights and head output.
+ * With FIT_SCALE_SYM the solver works on S A S and the adapter applies
+ * S^-1 M(S^-1 v).
+ *
+ * Blob format (fit_precond_save / _load): uint64 magic 0x3154454E55544946
+ * ("FITUNET1" little-endian), int32 c, int32 0, int64 nparams, then nparams
+ * fp32 parameters: for each layer in the order enc1a, enc1b, down1, enc2a,
+ * enc2b, down2, bot_a, bot_b, up2, dec2a, dec2b, up1, dec1a, dec1b, head, its
+ * weights w[tap][ci][co] (3x3x3 tap = (dz+1)*9 + (dy+1)*3 + (dx+1), 2x2x2
+ * tap = dz*4 + dy*2 + dx) and then its biases b[co].  Layer channel counts
+ * (cin -> cout): 12->c, c->c, c->2c, 2c->2c, 2c->2c, 2c->4c, 4c->4c, 4c->4c,
+ * 4c->2c, 4c->2c, 2c->2c, 2c->c, 2c->c, c->c, c->6. */
 
-/* Training configuration for fit_precond_train (all fields have defaults
- * when 0). */
+/* Configuration for fit_precond_create / fit_precond_train (0 = default). */
 typedef struct {
-  int32_t base_channels; /* channels of the first level (16) */
+  int32_t base_channels; /* c, one of 8, 16, 24, 32 (16) */
   int32_t steps;         /* optimiser steps (2000) */
-  int32_t batch;         /* crops per step (4) */
+  int32_t batch;         /* residual->error pairs per step (4) */
   int32_t crop;          /* crop edge in nodes, multiple of 4 (32) */
-  int32_t pairs_per_system; /* residual->error pairs harvested per system (200) */
-  int32_t seed;
+  int32_t pairs_per_system; /* reserved (0) */
+  int32_t seed;          /* initial weights and sampling */
   double lr;             /* Adam learning rate (1e-3) */
-  double weight_decay;
+  double weight_decay;   /* added to the gradient as weight_decay * w (0) */
   void *stream;
 } fit_precond_cfg;
 
-/* Train a preconditioner on residual->error pairs generated by plain solves on
- * the given grids and frequencies.  Synchronous. */
+/* Train a new preconditioner with Adam on residual->error pairs r = A(omega) e,
+ * where e is seeded complex noise on the free edges of one of the training
+ * grids, smoothed 2, 4, 8 or 16 times by averaging each edge value with the
+ * same component at the neighbouring nodes; one pair per sample, on a random
+ * crop of `crop` nodes per axis, at a random omega of `omegas`.  Loss: the mean
+ * over the crop's free edges of |U(r/s_r) - e/s_e|^2 with s_r, s_e the rms of
+ * r and e there.  Synchronous; *out receives the trained object.  The mean
+ * loss of every optimiser step is kept for fit_precond_train_history. */
 fit_status fit_precond_train(struct fit_grid *const *train, int ntrain, const double *omegas,
                              int nomega, const fit_precond_cfg *cfg, struct fit_precond **out);
-/* Create an untrained (randomly initialised, seeded) preconditioner. */
+/* Per-step mean training loss of this thread's last fit_precond_train:
+ * copies min(max, steps) values to out (may be NULL); *n = steps. */
+fit_status fit_precond_train_history(double *out, int max, int *n);
+/* Create an untrained preconditioner (seeded He-uniform weights, zero
+ * biases) on `device`. */
 fit_status fit_precond_create(const fit_precond_cfg *cfg, int device, struct fit_precond **out);
-/* Serialise (blob NULL: only report the size in *n) / deserialise weights. */
+/* Serialise to the blob format above (blob NULL: only report the size in *n;
+ * *n smaller than needed: FIT_E_INVALID and *n = size) / deserialise. */
 fit_status fit_precond_save(const struct fit_precond *p, void *blob, size_t *n);
 fit_status fit_precond_load(const void *blob, size_t n, int device, struct fit_precond **out);
-/* z = M(v) for one complex128 vector on grid g at omega (what FGMRES calls). */
+/* z = M(v) for one complex128 edge vector on grid g at omega (the unscaled
+ * form).  v_dev, z_dev: n_e complex128 on the grid's device.  Synchronous. */
 fit_status fit_precond_apply(struct fit_precond *p, const struct fit_grid *g, double omega,
                              const void *v_dev, void *z_dev, void *stream);
+/* Training objective of one pair over the whole grid (padded to multiples of
+ * 4 nodes): *loss = mean over free edges of |U(r/s_r) - e/s_e|^2 and its
+ * gradient with respect to the parameters, in blob order, as fp32 into the
+ * host array grad_host (nparams entries; may be NULL).  r_dev, e_dev: n_e
+ * complex128 on the device.  Synchronous. */
+fit_status fit_precond_loss_grad(struct fit_precond *p, const struct fit_grid *g, double omega,
+                                 const void *r_dev, const void *e_dev, double *loss,
+                                 float *grad_host, void *stream);
 void fit_precond_destroy(struct fit_precond *p);
 
 /* Thread-local message for the last failing call on this thread ("" if none). */

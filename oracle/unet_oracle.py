@@ -11,11 +11,13 @@ preconditioned directions.  Its definition is this module:
 
   * Spatial layout: the node grid (Nz, Ny, Nx) of the edge vector, channels
     last; the three edge components of a node are its channels.
-  * Input, 9 channels per node: Re/Im of the x, y and z edge values of v/s
+  * Input, 12 channels per node: Re/Im of the x, y and z edge values of v/s
     with s = rms of v over the free edges; eps_r / 12 and
     (log10(sigma + 1e-3) + 3) / 11 of the cell owned by the node (cell
-    (min(i, ncx-1), min(j, ncy-1), min(k, ncz-1))); log10(f / 1 GHz) / 1.6.
-  * Network (c = base channels): enc1a, enc1b (conv3, 9->c->c);
+    (min(i, ncx-1), min(j, ncy-1), min(k, ncz-1))); log10(f / 1 GHz) / 1.6;
+    log10(h / 100 um) of that cell's widths h = dx, dy, dz (the local mesh
+    scale, which sets the size of the curl-curl term).
+  * Network (c = base channels): enc1a, enc1b (conv3, 12->c->c);
     down1 (2x2x2 stride 2, c->2c); enc2a, enc2b (conv3, 2c); down2 (2c->4c);
     bot_a, bot_b (conv3, 4c); up2 (transposed 2x2x2 stride 2, 4c->2c);
     dec2a (conv3 on [up2, enc2b] = 4c -> 2c), dec2b (2c); up1 (2c->c);
@@ -39,7 +41,7 @@ import torch
 import torch.nn.functional as F
 
 LAYERS = [
-    # name, kind, cin multiplier (of c; 0 = the 9 input channels), cout multiplier (0 = 6 outputs)
+    # name, kind, cin multiplier (of c; 0 = the 12 input channels), cout multiplier (0 = 6 outputs)
     ("enc1a", "conv3", 0, 1), ("enc1b", "conv3", 1, 1), ("down1", "down2", 1, 2),
     ("enc2a", "conv3", 2, 2), ("enc2b", "conv3", 2, 2), ("down2", "down2", 2, 4),
     ("bot_a", "conv3", 4, 4), ("bot_b", "conv3", 4, 4), ("up2", "up2", 4, 2),
@@ -47,7 +49,7 @@ LAYERS = [
     ("dec1a", "conv3", 2, 1), ("dec1b", "conv3", 1, 1), ("head", "pw", 1, 0),
 ]
 TAPS = {"conv3": 27, "down2": 8, "up2": 8, "pw": 1}
-N_IN, N_OUT = 9, 6
+N_IN, N_OUT = 12, 6
 
 
 def layer_shapes(c: int = 16):
@@ -141,7 +143,7 @@ LAYER_FN = {"conv3": conv3, "down2": down2, "up2": up2, "pw": pw}
 
 
 def forward(params, x, bf16: bool = False):
-    """U-Net forward on x (Z, Y, X, 9) with Z, Y, X multiples of 4 (torch
+    """U-Net forward on x (Z, Y, X, 12) with Z, Y, X multiples of 4 (torch
     float64 tensors; params from unflatten, as torch tensors or arrays).
     Returns the (Z, Y, X, 6) head output."""
     rnd = (lambda t: torch.from_numpy(bf16_round(t.detach().numpy())) + (t - t.detach())) if bf16 \
@@ -180,7 +182,7 @@ def node_materials(dev):
 
 
 def features(dev, omega: float, v: np.ndarray, free: np.ndarray):
-    """The 9 input channels (Nz, Ny, Nx, 9) for the edge vector v, and s."""
+    """The 12 input channels (Nz, Ny, Nx, 12) for the edge vector v, and s."""
     nx, ny, nz = dev.nodes
     vf = np.where(free, v, 0.0)
     s = np.sqrt(np.sum(np.abs(vf) ** 2) / max(int(free.sum()), 1))
@@ -192,6 +194,12 @@ def features(dev, omega: float, v: np.ndarray, free: np.ndarray):
     x[..., 6] = eps / 12.0
     x[..., 7] = (np.log10(sig + 1e-3) + 3.0) / 11.0
     x[..., 8] = np.log10(omega / (2 * np.pi) / 1e9) / 1.6
+    i = np.minimum(np.arange(nx), dev.ncx - 1)
+    j = np.minimum(np.arange(ny), dev.ncy - 1)
+    k = np.minimum(np.arange(nz), dev.ncz - 1)
+    x[..., 9] = np.log10(dev.dx[i] / 1e-4)[None, None, :]
+    x[..., 10] = np.log10(dev.dy[j] / 1e-4)[None, :, None]
+    x[..., 11] = np.log10(dev.dz[k] / 1e-4)[:, None, None]
     return x, s
 
 

@@ -730,7 +730,16 @@ extern "C" fit_status fit_solve(fit_grid* g, double omega, const void* source_de
   fit_status result;
   IdentityPrecond ident;
   PrecondApply* pre = nullptr;
-  if (o.solver == FIT_FGMRES) pre = o.precond ? precond_apply_of(o.precond, g, omega) : &ident;
+  if (o.solver == FIT_FGMRES) {
+    pre = &ident;
+    if (o.precond) {
+      pre = precond_apply_of(o.precond, g, omega);
+      if (!pre) {
+        set_error("fit_solve: the preconditioner cannot serve this grid (device mismatch or no memory)");
+        return FIT_E_INVALID;
+      }
+    }
+  }
   if (!std::isfinite(bnorm)) {
     result = FIT_E_NAN;
   } else if (bnorm == 0.0) {

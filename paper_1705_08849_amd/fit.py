@@ -120,6 +120,9 @@ _SIGS = [
     ("fit_precond_apply", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
     ("fit_precond_destroy", None, [C.c_void_p]),
+    ("fit_precond_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                        C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
+    ("fit_precond_train_history", C.c_int, [C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int)]),
     ("fit_tile_set", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]),
     ("fit_autotune", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p,
                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -344,3 +347,96 @@ def sweep(grids: Sequence[Grid], omegas: Sequence[float], sources, tol: float = 
         out.append(a[off: off + nf * nrhs * p].reshape(nf, nrhs, p))
         off += nf * nrhs * p
     return st, out, [infos[q].as_dict() for q in range(ng * nf * nrhs)]
+
+
+PRECOND_MAGIC = 0x3154454E55544946
+
+
+class Precond:
+    """The learned FGMRES right preconditioner (``fit_precond_*``)."""
+
+    def __init__(self, h: C.c_void_p, device: int = 0):
+        self.h = h
+        self.device = device
+
+    @staticmethod
+    def _cfg(base_channels=16, steps=0, batch=0, crop=0, seed=0, lr=0.0, weight_decay=0.0,
+             stream=None):
+        return PrecondCfg(base_channels, steps, batch, crop, 0, seed, lr, weight_decay,
+                          _stream_ptr(stream))
+
+    @classmethod
+    def create(cls, base_channels: int = 16, seed: int = 0, device: int = 0):
+        h = C.c_void_p()
+        cfg = cls._cfg(base_channels=base_channels, seed=seed)
+        check(lib().fit_precond_create(C.byref(cfg), device, C.byref(h)), "fit_precond_create")
+        return cls(h, device)
+
+    @classmethod
+    def train(cls, grids: Sequence["Grid"], omegas: Sequence[float], **kw):
+        gh = (C.c_void_p * len(grids))(*[g.h.value for g in grids])
+        om = (C.c_double * len(omegas))(*[float(o) for o in omegas])
+        cfg = cls._cfg(**kw)
+        h = C.c_void_p()
+        check(lib().fit_precond_train(gh, len(grids), om, len(omegas), C.byref(cfg), C.byref(h)),
+              "fit_precond_train")
+        return cls(h, grids[0].device)
+
+    @staticmethod
+    def train_history() -> np.ndarray:
+        n = C.c_int()
+        check(lib().fit_precond_train_history(None, 0, C.byref(n)), "fit_precond_train_history")
+        out = (C.c_double * max(n.value, 1))()
+        check(lib().fit_precond_train_history(out, n.value, C.byref(n)), "fit_precond_train_history")
+        return np.array(out[: n.value])
+
+    def save(self) -> bytes:
+        n = C.c_size_t()
+        check(lib().fit_precond_save(self.h, None, C.byref(n)), "fit_precond_save")
+        buf = (C.c_char * n.value)()
+        check(lib().fit_precond_save(self.h, buf, C.byref(n)), "fit_precond_save")
+        return bytes(buf)
+
+    @classmethod
+    def load(cls, blob: bytes, device: int = 0):
+        h = C.c_void_p()
+        check(lib().fit_precond_load(blob, len(blob), device, C.byref(h)), "fit_precond_load")
+        return cls(h, device)
+
+    @staticmethod
+    def blob_from_params(base_channels: int, params: np.ndarray) -> bytes:
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        head = np.array([PRECOND_MAGIC], np.uint64).tobytes() + \
+            np.array([base_channels, 0], np.int32).tobytes() + np.array([p.size], np.int64).tobytes()
+        return head + p.tobytes()
+
+    def params(self) -> np.ndarray:
+        return np.frombuffer(self.save()[24:], dtype=np.float32).copy()
+
+    def apply(self, grid: "Grid", omega: float, v, z=None, stream=None):
+        torch = _torch()
+        if z is None:
+            z = torch.empty_like(v)
+        check(lib().fit_precond_apply(self.h, grid.h, float(omega), _dptr(v), _dptr(z),
+                                      _stream_ptr(stream)), "fit_precond_apply")
+        return z
+
+    def loss_grad(self, grid: "Grid", omega: float, r, e, stream=None):
+        loss = C.c_double()
+        n = self.params().size
+        g = np.zeros(n, np.float32)
+        check(lib().fit_precond_loss_grad(self.h, grid.h, float(omega), _dptr(r), _dptr(e),
+                                          C.byref(loss), g.ctypes.data_as(C.c_void_p),
+                                          _stream_ptr(stream)), "fit_precond_loss_grad")
+        return loss.value, g
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fit_precond_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

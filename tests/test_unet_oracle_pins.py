@@ -124,6 +124,7 @@ def test_features_and_homogeneity():
     x, s = U.features(dev, om, v, free)
     assert np.allclose(x[..., 6], 1.0 / 12.0) and np.allclose(x[..., 7], 0.0)
     assert np.allclose(x[..., 8], 1.0 / 1.6)
+    assert np.allclose(x[..., 9:12], 1.0)  # 1 mm cells: log10(1 mm / 100 um)
     assert abs(np.mean(np.sum(x[..., :6] ** 2, -1)) * 125 / free.sum() - 1.0) < 1e-12
     p = U.init_params(4, seed=3)
     z1 = U.apply(dev, om, p, v, free, c=4, bf16=False)
@@ -135,5 +136,5 @@ def test_features_and_homogeneity():
 def test_parameter_layout():
     assert U.n_params(16) == sum(t * ci * co + co for _, _, t, ci, co in U.layer_shapes(16))
     shapes = {n: (t, ci, co) for n, _, t, ci, co in U.layer_shapes(16)}
-    assert shapes["enc1a"] == (27, 9, 16) and shapes["dec2a"] == (27, 64, 32)
+    assert shapes["enc1a"] == (27, 12, 16) and shapes["dec2a"] == (27, 64, 32)
     assert shapes["up2"] == (8, 64, 32) and shapes["head"] == (1, 16, 6)
