@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "freq-points solved/sec at 1e-8 rel. residual; matvec GB/s vs HBM peak"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cocg_step1_c128.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pcocg_step1_c128.json")
 KERNEL_SOURCES = ["paper_1705_08849_amd/csrc/stencil.h", "paper_1705_08849_amd/csrc/krylov.h",
                   "paper_1705_08849_amd/csrc/fit_internal.h", "paper_1705_08849_amd/csrc/reduce.h"]
 
@@ -109,11 +109,11 @@ def ingest_counters(fetch_csv, write_csv, copy_bytes, commands):
         vals = [x for x in vals if x > 0.05 * top]
         return sum(vals) / len(vals), len(vals)
 
-    out = {"kernel": "cocg_step1_c128", "kernel_source_hash": kernel_source_hash(),
+    out = {"kernel": "pcocg_step1_c128", "kernel_source_hash": kernel_source_hash(),
            "commands": commands}
     for counter, path, key in (("FETCH_SIZE", fetch_csv, "fetch"), ("WRITE_SIZE", write_csv, "write")):
         acc = per_kernel(_counter_rows(path), counter)
-        kib, n = pick(acc, "stencil_kernel<double", "OpCocgP")
+        kib, n = pick(acc, "stencil_kernel<double", "OpCocgPX")
         cal_kib, _ = pick(acc, "neg")
         scale = (copy_bytes / 1024.0) / cal_kib
         out[f"{key}_kib_raw"] = kib
@@ -248,17 +248,17 @@ def main():
     ok = [i for i, _ in infos if i["status_name"] == "FIT_OK" and i["true_relres"] <= 1e-8]
     value = len(ok) / elapsed
 
-    kname = "cocg_step1_c128" if args.solver == "cocg" and args.precision == "fp64" else None
+    kname = "pcocg_step1_c128" if args.solver == "cocg" and args.precision == "fp64" else None
     if kname is None or kname not in stats:
         kname = max(stats, key=lambda k: stats[k][1]) if stats else None
     roof = None
     if kname:
         launches, total_ms = stats[kname]
         avg_s = total_ms / 1e3 / launches
-        # fused step-1 kernel: reads r and p_old, writes p_new and q (4 complex
-        # 3-vectors per node) plus the 1-byte cell ids
+        # fused step-1 kernel: reads r, p_old and x, writes p_new, q and x
+        # (6 complex 3-vectors per node) plus the 1-byte cell ids
         vec = 16 if kname.endswith("c128") else 8
-        passes = {"cocg_step1": 4, "bicgstab_step1": 6, "bicgstab_step2": 4,
+        passes = {"pcocg_step1": 6, "cocg_step1": 4, "bicgstab_step1": 6, "bicgstab_step2": 4,
                   "gmres_matvec": 3, "residual": 3, "matvec": 2}
         base = kname.rsplit("_", 1)[0]
         alg = n_nodes * 3 * vec * passes.get(base, 2) + n_cells

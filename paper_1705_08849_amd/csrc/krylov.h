@@ -36,6 +36,100 @@ struct CgState {
   int iter, max_iter, done, hist_len;
   double* hist;
   int reason, pad;
+  // deferred solution update of the fused step (OpCocgPX): x still lacks
+  // alpha * p[pbuf] when pend is set
+  int pend, pbuf;
+};
+
+// Mass-preconditioned COCG step 1 with the preconditioner recomputed in the
+// operator launch.  In the unscaled operator's staging the diagonal term is
+// d = -omega^2 M_eps,c per free edge, so m = 1/M_eps,c = -omega^2 / d costs no
+// memory traffic.  Input p = m .* r + beta p_old (stored for owned nodes),
+// output q = A p and p^T q.  The owned nodes also apply the previous
+// iteration's solution update x += alpha_prev p_old, one step late, which
+// saves the streaming update kernel two vector passes; the last update is
+// applied by cocg_fixup_kernel.
+template <class T>
+struct OpCocgPX {
+  const T *r, *p_old;
+  T *p_new, *q, *x;
+  CgState* st;
+  double* part;
+  T w2;  // omega^2
+  cx<T> beta, alpha_prev;
+  struct Raw {
+    cx<T> r[3], p[3], x[3];
+  };
+  static constexpr int NRED = 2;
+  static constexpr bool kFused = true;
+  __device__ bool skip() const { return *(volatile int*)&st->done != kRunning; }
+  __device__ void begin() {
+    beta = cx<T>{(T)st->beta.re, (T)st->beta.im};
+    alpha_prev = cx<T>{(T)st->alpha.re, (T)st->alpha.im};
+  }
+  __device__ void load(int64_t n, Raw& a) const {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      a.r[w] = ldc(r, 3 * n + w);
+      a.p[w] = ldc(p_old, 3 * n + w);
+    }
+  }
+  __device__ void load_own(int64_t n, Raw& a) const {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) a.x[w] = ldc(x, 3 * n + w);
+  }
+  __device__ void zero(Raw& a) const {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) a.r[w] = a.p[w] = cx<T>{T(0), T(0)};
+  }
+  template <class NC>
+  __device__ void input_coef(const Raw& a, const NC& nc, cx<T> (&xin)[3]) const {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const cx<T> d = nc.e[w];
+      const bool fr = (nc.mask >> w) & 1u;
+      const T a2 = fr ? d.re * d.re + d.im * d.im : T(1);
+      const T f = fr ? -w2 / a2 : T(0);
+      const cx<T> m{f * d.re, -f * d.im};
+      xin[w] = m * a.r[w] + beta * a.p[w];
+    }
+  }
+  __device__ void own_input_raw(int64_t n, const Raw& a, const cx<T> (&pv)[3]) const {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      stc(p_new, 3 * n + w, pv[w]);
+      stc(x, 3 * n + w, a.x[w] + alpha_prev * a.p[w]);
+    }
+  }
+  __device__ void consume(int64_t n, const cx<T> (&y)[3], const cx<T> (&pv)[3], double* acc) const {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      stc(q, 3 * n + w, y[w]);
+      const double pr = pv[w].re, pi = pv[w].im, yr = y[w].re, yi = y[w].im;
+      acc[0] += pr * yr - pi * yi;
+      acc[1] += pr * yi + pi * yr;
+    }
+  }
+  __host__ __device__ double* partials() const { return part; }
+  __device__ void finalize(const double* s) const {
+    const cx<double> gam{s[0], s[1]};
+    const double g2 = cabs2(gam);
+    st->pend = 0;  // this launch applied the pending update
+    if (!isfinite(g2)) {
+      st->done = kNan;
+      return;
+    }
+    if (g2 == 0.0) {
+      st->reason = 1;
+      st->done = kBreakdown;
+      return;
+    }
+    const cx<double> rho = st->rho;
+    st->alpha = cx<double>{(rho.re * gam.re + rho.im * gam.im) / g2,
+                           (rho.im * gam.re - rho.re * gam.im) / g2};
+    st->pend = 1;
+    st->pbuf = (st->iter & 1) ^ 1;
+  }
 };
 
 // COCG step 1: p = r + beta p_old on the fly (stored), q = A p, p^T q.
@@ -359,6 +453,10 @@ struct OpGmresMv {
   __device__ void finalize(const double*) const {}
 };
 
+template <class T>
+struct OpName<OpCocgPX<T>> {
+  static const char* get() { return sizeof(T) == 8 ? "pcocg_step1_c128" : "pcocg_step1_c64"; }
+};
 template <class T>
 struct OpName<OpCocgP<T>> {
   static const char* get() { return sizeof(T) == 8 ? "cocg_step1_c128" : "cocg_step1_c64"; }

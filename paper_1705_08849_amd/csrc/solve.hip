@@ -385,13 +385,19 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
   auto one_iter = [&](int parity) -> fit_status {
     T* p_old = V.p[parity];
     T* p_new = V.p[parity ^ 1];
-    OpCocgP<T> k1{pre ? z : V.r, p_old, p_new, q, c.cst, c.part, c.cnt, {}};
-    fit_status e = launch_op_stencil_mode<T>(c, false, k1);
-    if (e != FIT_OK) return e;
+    fit_status e;
+    if (pre) {
+      // fused form: m recomputed in the operator launch, x updated one step late
+      OpCocgPX<T> k1{V.r, p_old, p_new, q, V.x, c.cst, c.part, (T)(c.omega * c.omega), {}, {}};
+      if ((e = launch_op_stencil_mode<T>(c, false, k1)) != FIT_OK) return e;
+    } else {
+      OpCocgP<T> k1{V.r, p_old, p_new, q, c.cst, c.part, c.cnt, {}};
+      if ((e = launch_op_stencil_mode<T>(c, false, k1)) != FIT_OK) return e;
+    }
     const int tok = prof_begin(c.s);
     if (pre) {
-      hipLaunchKernelGGL((pcocg_update_kernel<T, false>), dim3((unsigned)nbn), dim3(256), 0, c.s,
-                         ne, V.x, V.r, z, p_new, q, mdiag, c.cst, c.part);
+      hipLaunchKernelGGL(pcocg_rupdate_kernel<T>, dim3((unsigned)nbn), dim3(256), 0, c.s, ne, V.r,
+                         q, mdiag, c.cst, c.part);
     } else {
       hipLaunchKernelGGL(cocg_update_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, V.x, V.r,
                          p_new, q, ne, c.cst, c.part, c.cnt);
@@ -401,7 +407,7 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
     FIT_HIP(launch_finish<3>(c.part, (int)(pre ? nbn : nb), CocgFinish{c.cst}, c.s));
     return FIT_OK;
   };
-  const double per_iter_bytes = node_bytes(c.g, pre ? 12 : 10, sizeof(T));
+  const double per_iter_bytes = node_bytes(c.g, 10, sizeof(T));
   if (check_every <= 0) check_every = 2 * std::max(1, std::min(100, (int)(4e8 / (double)ne)));
   if (check_every & 1) ++check_every;
   hipGraphExec_t gexec = nullptr;
@@ -464,6 +470,11 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
   if (gexec) (void)hipGraphExecDestroy(gexec);
   if (graph) (void)hipGraphDestroy(graph);
   if (ret != FIT_OK) return ret;
+  if (pre) {
+    hipLaunchKernelGGL(cocg_fixup_kernel<T>, dim3((unsigned)nbn), dim3(256), 0, c.s, ne, V.x,
+                       V.p[0], V.p[1], c.cst);
+    FIT_HIP(hipGetLastError());
+  }
   *done = stalled ? kBreakdown : c.h_cst->done;
   *iters = c.h_cst->iter;
   c.last_reason = stalled ? 9 : c.h_cst->reason;

@@ -505,6 +505,41 @@ __global__ void __launch_bounds__(256)
                              b - it.block0, it.nblk);
 }
 
+// Streaming half of the fused mass-preconditioned COCG iteration (after
+// OpCocgPX): r -= alpha q, and r^T (m .* r), ||r||^2 (z = m .* r is not
+// stored: the next operator launch recomputes m).
+template <class T>
+__global__ void __launch_bounds__(256)
+    pcocg_rupdate_kernel(int64_t n, T* r, const T* q, const T* m, CgState* st, double* part) {
+  __shared__ double lds[3 * 4];
+  if (*(volatile int*)&st->done != kRunning) return;
+  const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> rv = ldc(r, e) - al * ldc(q, e);
+    stc(r, e, rv);
+    const cx<T> zv = ldc(m, e) * rv;
+    const double rr = rv.re, ri = rv.im, zr = zv.re, zi = zv.im;
+    acc[0] += rr * zr - ri * zi;
+    acc[1] += rr * zi + ri * zr;
+    acc[2] += rr * rr + ri * ri;
+  }
+  block_partial<3>(acc, part, lds);
+}
+
+// The solution update still pending after the last fused step.
+template <class T>
+__global__ void __launch_bounds__(256)
+    cocg_fixup_kernel(int64_t n, T* x, const T* p0, const T* p1, CgState* st) {
+  if (!*(volatile int*)&st->pend) return;
+  const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
+  const T* p = st->pbuf ? p1 : p0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    stc(x, e, ldc(x, e) + al * ldc(p, e));
+}
+
 // Initial scalars of the mass-preconditioned COCG: rho = r^T z, ||r||^2.
 struct PcocgInitFinish {
   CgState* st;

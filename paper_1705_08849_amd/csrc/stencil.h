@@ -33,6 +33,8 @@
 //    back for owned nodes), and the output may feed fused dot products.
 #pragma once
 
+#include <type_traits>
+
 #include "fit_internal.h"
 #include "profile.h"
 #include "reduce.h"
@@ -162,6 +164,18 @@ __device__ __forceinline__ void stage_node(Staged<T>& st, const cx<T> (&xin)[3],
 //   double* partials() const;                       block partial sums
 //   void finalize(const double* sums) const;        scalar step (finish kernel)
 // ---------------------------------------------------------------------------
+// Ops that set kFused = true receive the node's coefficients when forming
+// their input (input_coef), prefetch extra data for owned nodes (load_own)
+// and see their raw data when storing owned inputs (own_input_raw).
+template <class Op, class = void>
+struct OpFused {
+  static constexpr bool value = false;
+};
+template <class Op>
+struct OpFused<Op, std::void_t<decltype(Op::kFused)>> {
+  static constexpr bool value = Op::kFused;
+};
+
 // Body of one workgroup: logical tile lb of the launch L on grid g.  Its
 // reduction partials go to op.partials() at index lb.
 template <class T, int BX, int BY, int MODE, class Op>
@@ -234,6 +248,9 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
   auto fetch = [&](int q, Pending& f) {
     const int qc = min(q, qmax);
     op.load(col + (int64_t)qc * plane, f.raw);
+    if constexpr (OpFused<Op>::value) {
+      if (owner) op.load_own(col + (int64_t)qc * plane, f.raw);
+    }
     f.ids = load_cell_ids_raw_inrange(g, il, jl, qc);
     f.z = zgeo_raw<T>(g, qc);
   };
@@ -246,9 +263,19 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
     const NodeCoef<T> nc = node_coef(cg, lo, hi, z.hzl, z.hzh, z.ivz, q, pcoef);
     lo = hi;
     cx<T> xin[3];
-    op.input(f.raw, xin);
+    if constexpr (OpFused<Op>::value) {
+      op.input_coef(f.raw, nc, xin);
+    } else {
+      op.input(f.raw, xin);
+    }
     stage_node<T, MODE>(sn, xin, nc);
-    if (owner && q >= kb && q < ke) op.own_input(col + (int64_t)q * plane, sn.xr);
+    if (owner && q >= kb && q < ke) {
+      if constexpr (OpFused<Op>::value) {
+        op.own_input_raw(col + (int64_t)q * plane, f.raw, sn.xr);
+      } else {
+        op.own_input(col + (int64_t)q * plane, sn.xr);
+      }
+    }
   };
   auto advance = [&]() {
 #pragma unroll
