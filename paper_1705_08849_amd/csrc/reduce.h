@@ -73,13 +73,28 @@ __device__ __forceinline__ void block_partial_at(double (&v)[N], double* partial
 // totals to f (thread 0).  F provides skip() (nothing was reduced) and
 // operator()(const double* sums).
 template <int N, class F>
-__global__ void __launch_bounds__(256) finish_kernel(const double* partials, int nblk, F f) {
-  __shared__ double lds[N * 4];
+__global__ void __launch_bounds__(1024) finish_kernel(const double* partials, int nblk, F f) {
+  // 1024 threads with four independent loads in flight each: the finish sits
+  // on the critical path of every Krylov iteration, so its latency counts
+  constexpr int NT = 1024, U = 4;
+  __shared__ double lds[N * (NT / 64)];
   if (f.skip()) return;
   double s[N];
 #pragma unroll
   for (int q = 0; q < N; ++q) s[q] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+  int b = threadIdx.x;
+  for (; b + (U - 1) * NT < nblk; b += U * NT) {
+    double v[U][N];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < N; ++q) v[u][q] = partials[(int64_t)(b + u * NT) * N + q];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < N; ++q) s[q] += v[u][q];
+  }
+  for (; b < nblk; b += NT) {
 #pragma unroll
     for (int q = 0; q < N; ++q) s[q] += partials[(int64_t)b * N + q];
   }
@@ -112,7 +127,7 @@ __global__ void __launch_bounds__(256) finish_multi_kernel(const FinishItem<F>* 
 
 template <int N, class F>
 inline hipError_t launch_finish(const double* partials, int nblk, const F& f, hipStream_t s) {
-  hipLaunchKernelGGL((finish_kernel<N, F>), dim3(1), dim3(256), 0, s, partials, nblk, f);
+  hipLaunchKernelGGL((finish_kernel<N, F>), dim3(1), dim3(1024), 0, s, partials, nblk, f);
   return hipGetLastError();
 }
 
