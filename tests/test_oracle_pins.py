@@ -6,6 +6,8 @@ conservation (energy) identity, an invariance, a brute-force dense solve or a
 count that follows from the geometry.  The mutation tests at the end plant
 plausible mistakes in the oracle and check that some pin catches each.
 """
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -450,3 +452,29 @@ def test_mutation_half_cell_at_boundary_is_caught(monkeypatch):
         return nu * 1.0000001  # tiny global scale error of the reluctances
     monkeypatch.setattr(O, "facet_reluctance", bad)
     assert {"spectrum", "nu_energy"} <= set(_run_pins())
+
+
+def _paper_edge_counts():
+    rows = []
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_edge_counts.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        *_, nx, ny, nz, ne = line.split()
+        rows.append((int(nx), int(ny), int(nz), int(ne)))
+    return rows
+
+
+def test_edge_count_reading_matches_the_paper():
+    """n_e printed in Sec. IV equals 3 Nx Ny Nz with N counted in nodes; for
+    the meshes small enough to assemble, the oracle's curl has exactly that
+    many rows and columns, and a device of N-1 cells per axis reports it."""
+    rows = _paper_edge_counts()
+    assert len(rows) == 4
+    for nx, ny, nz, ne in rows:
+        assert 3 * nx * ny * nz == ne
+        if ne < 1_000_000:
+            c = O.curl(nx, ny, nz)
+            assert c.shape == (ne, ne)
+            dev = D.cavity(nx - 1, ny - 1, nz - 1)
+            assert dev.n_edges == ne
