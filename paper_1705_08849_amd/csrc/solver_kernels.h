@@ -509,14 +509,12 @@ __global__ void __launch_bounds__(256)
 // OpCocgPX): r -= alpha q, and r^T (m .* r), ||r||^2 (z = m .* r is not
 // stored: the next operator launch recomputes m).
 template <class T>
-__global__ void __launch_bounds__(256)
-    pcocg_rupdate_kernel(int64_t n, T* r, const T* q, const T* m, CgState* st, double* part) {
+__device__ __forceinline__ void pcocg_rupdate_body(int64_t n, T* r, const T* q, const T* m, CgState* st,
+                                                   double* part, int bid, int nblk) {
   __shared__ double lds[3 * 4];
-  if (*(volatile int*)&st->done != kRunning) return;
   const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = (int64_t)bid * blockDim.x + threadIdx.x; e < n; e += (int64_t)nblk * blockDim.x) {
     const cx<T> rv = ldc(r, e) - al * ldc(q, e);
     stc(r, e, rv);
     const cx<T> zv = ldc(m, e) * rv;
@@ -525,7 +523,29 @@ __global__ void __launch_bounds__(256)
     acc[1] += rr * zi + ri * zr;
     acc[2] += rr * rr + ri * ri;
   }
-  block_partial<3>(acc, part, lds);
+  block_partial_at<3>(acc, part, lds, bid);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256)
+    pcocg_rupdate_kernel(int64_t n, T* r, const T* q, const T* m, CgState* st, double* part) {
+  if (*(volatile int*)&st->done != kRunning) return;
+  pcocg_rupdate_body<T>(n, r, q, m, st, part, blockIdx.x, gridDim.x);
+}
+
+// The same for several systems in one launch (PcocgItem: r, q, m, st, part).
+template <class T>
+__global__ void __launch_bounds__(256)
+    pcocg_rupdate_multi_kernel(const PcocgItem<T>* __restrict__ items, int nitems) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].block0 <= b) lo = mid; else hi = mid - 1;
+  }
+  const PcocgItem<T> it = items[lo];
+  if (*(volatile int*)&it.st->done != kRunning) return;
+  pcocg_rupdate_body<T>(it.n, it.r, it.q, it.m, it.st, it.part, b - it.block0, it.nblk);
 }
 
 // The solution update still pending after the last fused step.

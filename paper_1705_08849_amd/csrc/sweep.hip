@@ -5,8 +5,9 @@
 // COCG iteration (the same method and recurrences as fit_solve's COCG) for
 // all of its systems at once: one iteration is four launches whatever the
 // batch size -- one operator launch covering every system's tiles (the grids
-// may differ), one finish launch with a block per system, one streaming
-// update launch and one more finish launch.  The loop of `check_every`
+// may differ; it also recomputes the preconditioner and applies the previous
+// solution update, as in fit_solve), one finish launch with a block per
+// system, one streaming residual-update launch and one more finish launch.  The loop of `check_every`
 // iterations is captured once as a hipGraph and replayed.  Every system
 // keeps its own scalars and done flag on the device, so a converged system
 // drops out at once (its blocks return immediately); the graph is captured
@@ -162,8 +163,8 @@ struct BatchGraph {
 // Device-side launch tables of one captured batch, in precision T.
 template <class T>
 struct Tables {
-  MultiItem<OpCocgP<T>>* stencil[2] = {nullptr, nullptr};  // by parity
-  FinishItem<OpFinish<OpCocgP<T>>>* fin1[2] = {nullptr, nullptr};
+  MultiItem<OpCocgPX<T>>* stencil[2] = {nullptr, nullptr};  // by parity
+  FinishItem<OpFinish<OpCocgPX<T>>>* fin1[2] = {nullptr, nullptr};
   PcocgItem<T>* upd[2] = {nullptr, nullptr};
   FinishItem<CocgFinish>* fin2 = nullptr;
   int n = 0, stencil_blocks = 0, upd_blocks = 0;
@@ -180,8 +181,8 @@ fit_status build_tables(std::vector<Sys*>& act, Tables<T>& t, void* dev_buf, hip
     if (y->g->ne > big->g->ne) big = y;
   t.shape = tile_for(big->g, dtype);
   const int n = (int)act.size();
-  std::vector<MultiItem<OpCocgP<T>>> st[2];
-  std::vector<FinishItem<OpFinish<OpCocgP<T>>>> f1[2];
+  std::vector<MultiItem<OpCocgPX<T>>> st[2];
+  std::vector<FinishItem<OpFinish<OpCocgPX<T>>>> f1[2];
   std::vector<PcocgItem<T>> up[2];
   std::vector<FinishItem<CocgFinish>> f2;
   int sb = 0, ub = 0;
@@ -199,9 +200,10 @@ fit_status build_tables(std::vector<Sys*>& act, Tables<T>& t, void* dev_buf, hip
     for (int par = 0; par < 2; ++par) {
       T* p_old = (T*)y.p[par];
       T* p_new = (T*)y.p[par ^ 1];
-      OpCocgP<T> op{(const T*)y.z, p_old, p_new, (T*)y.q, y.st, y.part, y.cnt, {}};
-      st[par].push_back(MultiItem<OpCocgP<T>>{y.g->view, L, op, sb, nb});
-      f1[par].push_back(FinishItem<OpFinish<OpCocgP<T>>>{y.part, nb, OpFinish<OpCocgP<T>>{op}});
+      OpCocgPX<T> op{(const T*)y.ri, p_old, p_new, (T*)y.q, (T*)y.d, y.st, y.part,
+                     (T)(y.omega * y.omega), {}, {}};
+      st[par].push_back(MultiItem<OpCocgPX<T>>{y.g->view, L, op, sb, nb});
+      f1[par].push_back(FinishItem<OpFinish<OpCocgPX<T>>>{y.part, nb, OpFinish<OpCocgPX<T>>{op}});
       up[par].push_back(PcocgItem<T>{y.g->ne, (T*)y.d, (T*)y.ri, (T*)y.z, p_new, (const T*)y.q,
                                      (const T*)y.m, y.st, y.part, ub, nu});
     }
@@ -234,8 +236,8 @@ fit_status build_tables(std::vector<Sys*>& act, Tables<T>& t, void* dev_buf, hip
 
 template <class T>
 size_t table_bytes(int n) {
-  return 2 * (align_up(sizeof(MultiItem<OpCocgP<T>>) * n, 256) +
-              align_up(sizeof(FinishItem<OpFinish<OpCocgP<T>>>) * n, 256) +
+  return 2 * (align_up(sizeof(MultiItem<OpCocgPX<T>>) * n, 256) +
+              align_up(sizeof(FinishItem<OpFinish<OpCocgPX<T>>>) * n, 256) +
               align_up(sizeof(PcocgItem<T>) * n, 256)) +
          align_up(sizeof(FinishItem<CocgFinish>) * n, 256) + 4096;
 }
@@ -246,12 +248,12 @@ fit_status one_iter(const Tables<T>& t, int par, hipStream_t s) {
                                                 sizeof(T) == 8 ? "sweep_cocg_step1_c128"
                                                                : "sweep_cocg_step1_c64");
   if (e != FIT_OK) return e;
-  hipLaunchKernelGGL((finish_multi_kernel<2, OpFinish<OpCocgP<T>>>), dim3(t.n), dim3(256), 0, s,
+  hipLaunchKernelGGL((finish_multi_kernel<2, OpFinish<OpCocgPX<T>>>), dim3(t.n), dim3(256), 0, s,
                      t.fin1[par]);
   FIT_HIP(hipGetLastError());
   const int tok = prof_begin(s);
-  hipLaunchKernelGGL((pcocg_update_multi_kernel<T, false>), dim3(t.upd_blocks), dim3(256), 0, s,
-                     t.upd[par], t.n);
+  hipLaunchKernelGGL(pcocg_rupdate_multi_kernel<T>, dim3(t.upd_blocks), dim3(256), 0, s, t.upd[par],
+                     t.n);
   FIT_HIP(hipGetLastError());
   prof_end(tok, s, sizeof(T) == 8 ? "sweep_cocg_update_c128" : "sweep_cocg_update_c64");
   hipLaunchKernelGGL((finish_multi_kernel<3, CocgFinish>), dim3(t.n), dim3(256), 0, s, t.fin2);
@@ -391,6 +393,12 @@ fit_status run_batch(std::vector<Sys*>& sys, double tol, const fit_solve_opts& o
       run.swap(still);
     }
 
+    // the fused step leaves the last solution update pending
+    for (Sys* yp : act) {
+      hipLaunchKernelGGL(cocg_fixup_kernel<T>, dim3((unsigned)pw_blocks(yp->g->ne)), dim3(256), 0, s,
+                         yp->g->ne, (T*)yp->d, (const T*)yp->p[0], (const T*)yp->p[1], yp->st);
+      FIT_HIP(hipGetLastError());
+    }
     // x += eta d, true residual, decisions
     for (Sys* yp : act) {
       Sys& y = *yp;
@@ -398,7 +406,7 @@ fit_status run_batch(std::vector<Sys*>& sys, double tol, const fit_solve_opts& o
       y.iters += y.inner_iters;
       y.matvecs += y.inner_iters + 1;
       y.refin += 1;
-      y.bytes += (double)y.inner_iters * ((double)y.g->view.np * 3.0 * sizeof(T) * 2 * 12);
+      y.bytes += (double)y.inner_iters * ((double)y.g->view.np * 3.0 * sizeof(T) * 2 * 10);
       if (y.inner_done == kNan) {
         y.status = FIT_E_NAN;
         y.running = false;
