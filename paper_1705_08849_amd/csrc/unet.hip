@@ -610,7 +610,7 @@ fit_status gemm(const GemmArgs& g, int64_t n_cols, hipStream_t s, int splits = 1
   const int64_t kpad = pad32(a.K);
   if (splits < 1) splits = 1;
   a.k_chunk = pad32((kpad + splits - 1) / splits);
-  const dim3 grid((unsigned)((a.M + 63) / 64), (unsigned)((n_cols + nt - 1) / nt), (unsigned)splits);
+  const dim3 grid((unsigned)((a.M + 127) / 128), (unsigned)((n_cols + nt - 1) / nt), (unsigned)splits);
   const int tok = prof_begin(s);
   if (nt == 16)
     hipLaunchKernelGGL(igemm_kernel<16>, grid, dim3(256), 0, s, a);

@@ -14,11 +14,14 @@
 // scatter the 8 children of a transposed 2x2x2 convolution, accumulate into
 // fp32 gradients, or write split-K partial sums.
 //
-// Tiling for CDNA4: a 256-thread workgroup computes 64 rows x NT columns; each
-// wavefront owns 16 rows and NT/16 accumulators of the 16x16x32 bf16 MFMA.
-// Each lane loads its 8 consecutive K values of A (one 16-byte load, since
-// channel counts are multiples of 8) and of B, so no LDS staging is needed:
-// the 27-fold reuse of an input voxel across taps is served by L1/L2.
+// Tiling for CDNA4: a 256-thread workgroup computes 128 rows x NT columns;
+// each wavefront owns two 16-row subtiles and 2 x NT/16 accumulators of the
+// 16x16x32 bf16 MFMA, so each B fragment feeds two MFMAs.  Each lane loads
+// its 8 consecutive K values of A (one 16-byte load, since channel counts are
+// multiples of 8) and of B, so no LDS staging is needed: the 27-fold reuse of
+// an input voxel across taps is served by L1/L2.  The gather walks K with a
+// per-lane (tap, channel) cursor; a tap's element offset is one add, and the
+// row's bounds are three bit tests.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -61,99 +64,149 @@ struct GemmArgs {
   int64_t k_chunk;    // K per split (multiple of 32); gridDim.z splits
 };
 
+// Per-lane gather cursor over K: the current tap, the channel offset inside
+// the tap, and the tap's element offset (uniform over the lanes that share
+// the K position; the bounds test is per row).
+struct KCursor {
+  int tap, ci;
+};
+
 template <int NT>
 __global__ void __launch_bounds__(256) igemm_kernel(GemmArgs p) {
-  constexpr int NS = NT / 16;
+  constexpr int NS = NT / 16;  // N subtiles per wave
+  constexpr int MS = 2;        // 16-row M subtiles per wave
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t m_tile = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t m_tile = (int64_t)blockIdx.x * (64 * MS) + wave * (16 * MS);
   const int n0 = blockIdx.y * NT;
   const int64_t kb = (int64_t)blockIdx.z * p.k_chunk;
   const int64_t ke0 = kb + p.k_chunk;
   const int64_t kpad = (p.K + 31) / 32 * 32;
   const int64_t ke = ke0 < kpad ? ke0 : kpad;
-
-  // this lane's A row and its decoded coordinates
-  const int64_t m = m_tile + (lane & 15);
-  const bool mv = m < p.M;
-  int mx = 0, my = 0, mz = 0;
-  if (p.gather != G_PW && mv) {
-    mx = (int)(m % p.ox);
-    my = (int)((m / p.ox) % p.oy);
-    mz = (int)(m / ((int64_t)p.ox * p.oy));
-  }
   const int kq = 8 * (lane >> 4);
+  const bool pw = p.gather == G_PW, conv3 = p.gather == G_CONV3;
 
-  floatx4 acc[NS];
+  // rows of this lane: base element of its first tap and per-axis validity
+  const bf16* base[MS];
+  uint32_t okx[MS], oky[MS], okz[MS];  // bit j: offset j-1 (conv3) or j (down2) in range
+  bool mv[MS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) acc[s] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int s = 0; s < MS; ++s) {
+    const int64_t m = m_tile + 16 * s + (lane & 15);
+    mv[s] = m < p.M;
+    const int64_t mm = mv[s] ? m : 0;
+    okx[s] = oky[s] = okz[s] = 7u;
+    if (pw) {
+      base[s] = p.a + mm * p.a_ld;
+    } else {
+      const int mx = (int)(mm % p.ox), my = (int)((mm / p.ox) % p.oy), mz = (int)(mm / ((int64_t)p.ox * p.oy));
+      if (conv3) {
+        base[s] = p.a + (((int64_t)mz * p.iy + my) * p.ix + mx) * p.a_ld;
+        okx[s] = (mx > 0 ? 1u : 0u) | 2u | (mx + 1 < p.ix ? 4u : 0u);
+        oky[s] = (my > 0 ? 1u : 0u) | 2u | (my + 1 < p.iy ? 4u : 0u);
+        okz[s] = (mz > 0 ? 1u : 0u) | 2u | (mz + 1 < p.iz ? 4u : 0u);
+      } else {
+        base[s] = p.a + (((int64_t)(2 * mz) * p.iy + 2 * my) * p.ix + 2 * mx) * p.a_ld;
+      }
+    }
+  }
+  // K cursor of this lane
+  KCursor cur{0, 0};
+  if (!pw) {
+    const int64_t k0 = kb + kq;
+    cur.tap = (int)(k0 / p.cin);
+    cur.ci = (int)(k0 % p.cin);
+  }
+  const int64_t sx = p.a_ld, sy = (int64_t)p.ix * p.a_ld, sz = (int64_t)p.iy * p.ix * p.a_ld;
+
+  floatx4 acc[MS][NS];
+#pragma unroll
+  for (int s = 0; s < MS; ++s)
+#pragma unroll
+    for (int t = 0; t < NS; ++t) acc[s][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   for (int64_t kk = kb; kk < ke; kk += 32) {
     const int64_t k = kk + kq;
-    bf16x8 av;
+    const bool kv = k < p.K;
+    // element offset of this lane's tap and the per-row validity bit
+    int64_t off;
+    int jx = 1, jy = 1, jz = 1;
+    if (pw) {
+      off = k;
+    } else if (conv3) {
+      const int dz = cur.tap / 9, r9 = cur.tap - 9 * dz, dy = r9 / 3, dx = r9 - 3 * dy;
+      jx = dx;
+      jy = dy;
+      jz = dz;
+      off = (dz - 1) * sz + (dy - 1) * sy + (dx - 1) * sx + cur.ci;
+    } else {
+      const int dx = cur.tap & 1, dy = (cur.tap >> 1) & 1, dz = cur.tap >> 2;
+      off = dz * sz + dy * sy + dx * sx + cur.ci;
+    }
+    bf16x8 av[MS];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) av[e] = (bf16)0.0f;
-    if (mv && k < p.K) {
-      const bf16* src = nullptr;
-      if (p.gather == G_PW) {
-        src = p.a + m * p.a_ld + k;
+    for (int s = 0; s < MS; ++s) {
+      bool ok = mv[s] && kv;
+      if (conv3) ok = ok && ((okx[s] >> jx) & (oky[s] >> jy) & (okz[s] >> jz) & 1u);
+      if (ok) {
+        av[s] = *reinterpret_cast<const bf16x8*>(base[s] + off);
       } else {
-        const int tap = (int)(k / p.cin), ci = (int)(k % p.cin);
-        int x, y, z;
-        if (p.gather == G_CONV3) {
-          x = mx + tap % 3 - 1;
-          y = my + (tap / 3) % 3 - 1;
-          z = mz + tap / 9 - 1;
-        } else {
-          x = 2 * mx + (tap & 1);
-          y = 2 * my + ((tap >> 1) & 1);
-          z = 2 * mz + (tap >> 2);
-        }
-        if (x >= 0 && y >= 0 && z >= 0 && x < p.ix && y < p.iy && z < p.iz)
-          src = p.a + (((int64_t)z * p.iy + y) * p.ix + x) * p.a_ld + ci;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[s][e] = (bf16)0.0f;
       }
-      if (src) av = *reinterpret_cast<const bf16x8*>(src);
     }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int n = n0 + s * 16 + (lane & 15);
+    for (int t = 0; t < NS; ++t) {
+      const int n = n0 + t * 16 + (lane & 15);
       const bf16x8 bv = *reinterpret_cast<const bf16x8*>(p.b + (int64_t)n * p.ldb + k);
-      acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[s], 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < MS; ++s)
+        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], bv, acc[s][t], 0, 0, 0);
+    }
+    if (!pw) {  // advance the cursor by 32 K positions
+      cur.ci += 32;
+      while (cur.ci >= p.cin) {
+        cur.ci -= p.cin;
+        ++cur.tap;
+      }
     }
   }
 
-  // epilogue: lane holds rows m_tile + 4*(lane/16) + r, column n0 + 16 s + lane%16
+  // epilogue: lane holds rows m_tile + 16 s + 4*(lane/16) + r, column n0 + 16 t + lane%16
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int n = n0 + s * 16 + (lane & 15);
-    if (n >= p.N) continue;
+  for (int s = 0; s < MS; ++s) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = m_tile + 4 * (lane >> 4) + r;
-      if (row >= p.M) continue;
-      float v = acc[s][r];
-      if (p.out == O_PART) {
-        p.o32[((int64_t)blockIdx.z * p.M + row) * p.N + n] = v;
-        continue;
+    for (int t = 0; t < NS; ++t) {
+      const int n = n0 + t * 16 + (lane & 15);
+      if (n >= p.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m_tile + 16 * s + 4 * (lane >> 4) + r;
+        if (row >= p.M) continue;
+        float v = acc[s][t][r];
+        if (p.out == O_PART) {
+          p.o32[((int64_t)blockIdx.z * p.M + row) * p.N + n] = v;
+          continue;
+        }
+        int64_t vox = row;
+        int ch = n;
+        if (p.up) {
+          const int tt = n / p.up_c;
+          ch = n % p.up_c;
+          const int ux = (int)(row % p.ox), uy = (int)((row / p.ox) % p.oy),
+                    uz = (int)(row / ((int64_t)p.ox * p.oy));
+          const int cx = 2 * ux + (tt & 1), cy = 2 * uy + ((tt >> 1) & 1), cz = 2 * uz + (tt >> 2);
+          vox = ((int64_t)cz * p.up_y + cy) * p.up_x + cx;
+        }
+        if (p.bias) v += p.bias[ch];
+        if (p.relu) v = v > 0.f ? v : 0.f;
+        const int64_t dst = vox * p.o_ld + ch;
+        if (p.out == O_BF16)
+          p.o16[dst] = (bf16)v;
+        else if (p.out == O_F32)
+          p.o32[dst] = v;
+        else
+          p.o32[dst] += v;
       }
-      int64_t vox = row;
-      int ch = n;
-      if (p.up) {
-        const int t = n / p.up_c;
-        ch = n % p.up_c;
-        const int ux = (int)(row % p.ox), uy = (int)((row / p.ox) % p.oy),
-                  uz = (int)(row / ((int64_t)p.ox * p.oy));
-        const int cx = 2 * ux + (t & 1), cy = 2 * uy + ((t >> 1) & 1), cz = 2 * uz + (t >> 2);
-        vox = ((int64_t)cz * p.up_y + cy) * p.up_x + cx;
-      }
-      if (p.bias) v += p.bias[ch];
-      if (p.relu) v = v > 0.f ? v : 0.f;
-      const int64_t dst = vox * p.o_ld + ch;
-      if (p.out == O_BF16)
-        p.o16[dst] = (bf16)v;
-      else if (p.out == O_F32)
-        p.o32[dst] = v;
-      else
-        p.o32[dst] += v;
     }
   }
 }
