@@ -127,6 +127,113 @@ def ingest_counters(fetch_csv, write_csv, copy_bytes, commands):
     print(json.dumps(out, indent=1))
 
 
+def sweep_row(fit, D, np, torch, with_cpu):
+    """The batched sweep (fit_sweep) against the same systems solved one
+    fit_solve at a time, on the smallest sweep-family grid."""
+    sd = D.sweep_devices(seeds=[40], shapes=[(64, 64, 32)])[0]
+    g = fit.Grid(sd)
+    oms = D.log_spaced_omegas(16, 5e9, 40e9)
+    g.autotune("c128", "none", float(oms[8]), reps=3)
+    src = torch.from_numpy(D.port_source(sd, 0)).to("cuda:0")
+    fit.sweep([g], oms[:2], [src[None, :]], tol=1e-8)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, _, infos = fit.sweep([g], oms, [src[None, :]], tol=1e-8, precision="fp64")
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for om in oms:
+        g.solve(float(om), src, tol=1e-8, solver="cocg", raise_on_error=False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    iters = [i["iterations"] for i in infos]
+    row = {"workload": "64x64x32-cell sweep-family device (seed 40), 16 log-spaced frequencies "
+                       "5-40 GHz, one port excitation, COCG fp64 to 1e-8",
+           "status": fit.STATUS_NAMES[st], "points": 16, "batched_points_per_s": round(16 / tb, 3),
+           "sequential_points_per_s": round(16 / ts, 3), "speedup": round(ts / tb, 3),
+           "iterations": [min(iters), max(iters)]}
+    if with_cpu:
+        import scipy.sparse as sp
+        from threadpoolctl import threadpool_limits
+
+        from oracle import fit_oracle as O
+        om = float(oms[8])
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            a = O.system_matrix(sd, om)
+            s = O.sym_scaling(sd, om)
+            as_ = (sp.diags(s) @ a @ sp.diags(s)).tocsr()
+            b = s * O.rhs(sd, om, D.port_source(sd, 0))
+            t1 = time.perf_counter()
+            O.cocg(as_, b, tol=1e-30, maxiter=20)
+            t2 = time.perf_counter()
+        per_point = (t1 - t0) + (t2 - t1) / 20 * float(np.mean(iters))
+        row["cpu_baseline"] = {"value": round(1.0 / per_point, 5), "unit": "freq-points/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "assembly + 20 COCG iterations at the middle frequency on one "
+                                         "host thread, extrapolated with the GPU's mean iteration count"}
+    return row
+
+
+def precond_row(fit, D, np, torch, with_cpu):
+    """The learned preconditioner: one application on the 192x192x96-cell
+    family device against the BF16 MFMA peak, and one training step."""
+    fd = D.learned_family_device(9000)
+    g = fit.Grid(fd)
+    c = 16
+    pre = fit.Precond.create(base_channels=c, seed=1)
+    v = torch.randn(fd.n_edges, dtype=torch.complex128, device="cuda:0")
+    om = 2 * np.pi * 1e10
+    pre.apply(g, om, v)
+    torch.cuda.synchronize()
+    n = 5
+    t0 = time.perf_counter()
+    for _ in range(n):
+        pre.apply(g, om, v)
+    torch.cuda.synchronize()
+    ta = (time.perf_counter() - t0) / n
+    X, Y, Z = [(k + 1 + 3) // 4 * 4 for k in (fd.ncx, fd.ncy, fd.ncz)]
+    v1 = X * Y * Z
+    # (K, N, rows) of the 15 GEMMs of one forward pass
+    lay = [(27 * 16, c, v1), (27 * c, c, v1), (8 * c, 2 * c, v1 / 8), (27 * 2 * c, 2 * c, v1 / 8),
+           (27 * 2 * c, 2 * c, v1 / 8), (8 * 2 * c, 4 * c, v1 / 64), (27 * 4 * c, 4 * c, v1 / 64),
+           (27 * 4 * c, 4 * c, v1 / 64), (4 * c, 16 * c, v1 / 64), (27 * 4 * c, 2 * c, v1 / 8),
+           (27 * 2 * c, 2 * c, v1 / 8), (2 * c, 8 * c, v1 / 8), (27 * 2 * c, c, v1),
+           (27 * c, c, v1), (c, 6, v1)]
+    flops = sum(2.0 * k * nn * m for k, nn, m in lay)
+    sd = D.layered_device(48, 48, 32, n_layers=4, n_strips=3, n_ports=1, seed=4)
+    gt = fit.Grid(sd)
+    fit.Precond.train([gt], [2 * np.pi * 5e9], base_channels=c, steps=2, batch=4, crop=32, seed=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fit.Precond.train([gt], [2 * np.pi * 5e9], base_channels=c, steps=20, batch=4, crop=32, seed=3)
+    torch.cuda.synchronize()
+    tt = (time.perf_counter() - t0) / 20
+    row = {"workload": "3-level U-Net (c=16) preconditioner application on the 192x192x96-cell "
+                       "family device (seed 9000); training steps of 4 crops of 32^3 nodes",
+           "apply_ms": round(ta * 1e3, 3),
+           "roofline": {"bound": "mfma", "achieved": round(flops / ta / 1e12, 2), "peak": 2500.0,
+                        "unit": "TFLOP/s", "frac": round(flops / ta / 1e12 / 2500.0, 4),
+                        "traffic": None},
+           "train_step_ms": round(tt * 1e3, 3)}
+    if with_cpu:
+        from oracle import fit_oracle as O
+        from oracle import unet_oracle as U
+        small = D.layered_device(47, 47, 23, n_layers=3, n_strips=2, n_ports=1, seed=6)
+        free = O.free_edges(small)
+        p = U.init_params(c, seed=1)
+        vv = np.where(free, 1.0 + 0.0j, 0.0)
+        t0 = time.perf_counter()
+        U.apply(small, om, p, vv, free, c=c, bf16=False)
+        tc = time.perf_counter() - t0
+        scale = v1 / (48 * 48 * 24)
+        row["cpu_baseline"] = {"value": round(1.0 / (tc * scale), 5), "unit": "applications/s",
+                               "cores": int(__import__("torch").get_num_threads()), "kind": "oracle",
+                               "sample": "one oracle application (plain PyTorch CPU fp64) on a "
+                                         "48x48x24-node device, scaled by voxel count"}
+    return row
+
+
 def cpu_baseline(dev, omega, src, gpu_iters):
     """The FP64 oracle as it stands, one thread: assemble and scale the
     system, time 5 COCG iterations, extrapolate one solve with the GPU's
@@ -170,6 +277,8 @@ def main():
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the secondary rows (batched sweep, learned preconditioner)")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short sample profiled by the HBM-counter passes")
     ap.add_argument("--ingest", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_BYTES"),
@@ -306,6 +415,11 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dev, omega, src_np, iters)
+    if not args.no_rows:
+        del g
+        torch.cuda.empty_cache()
+        out["rows"] = {"sweep": sweep_row(fit, D, np, torch, not args.no_cpu_baseline),
+                       "precond": precond_row(fit, D, np, torch, not args.no_cpu_baseline)}
     print(json.dumps(out), flush=True)
 
 
