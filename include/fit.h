@@ -253,12 +253,12 @@ fit_status fit_port_voltages(const struct fit_grid *g, const void *x_dev, int nv
 /* ---- stencil launch shapes and the autotuner ------------------------------
  * A workgroup of tx x ty threads covers tx x ty node columns -- the
  * (tx-2) x (ty-2) columns it outputs plus a one-node halo ring -- and marches
- * up zc z-planes.  Compiled shapes: (tx, ty) in {(64,8), (48,8), (32,8),
- * (32,16)}.  The table is process-wide and keyed by the grid's node
- * dimensions and dtype. */
+ * up zc z-planes, 1 <= zc <= 128.  Compiled shapes: (tx, ty) in {(64,8),
+ * (48,8), (32,8), (32,16)}.  The table is process-wide and keyed by the
+ * grid's node dimensions and dtype. */
 
 /* Force a tile shape for grids of g's node dimensions in `dtype`.
- * FIT_E_INVALID for a shape that is not compiled or zc < 1. */
+ * FIT_E_INVALID for a shape that is not compiled or zc outside [1, 128]. */
 fit_status fit_tile_set(const struct fit_grid *g, int dtype, int tx, int ty, int zc);
 
 /* Time every compiled (TX, TY) with a range of ZC on g (operator in `dtype`

@@ -85,6 +85,9 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Largest z-chunk a block marches (its planes' z-geometry sits in LDS).
+constexpr int kMaxZChunk = 128;
+
 struct StencilLaunch {
   int nbx, nby, nbz, zc;
   double omega;
@@ -217,10 +220,20 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
   const int64_t plane = (int64_t)g.nx * g.ny;
 
   fill_mat_mode<T>(mat, g.mats, L.omega, MODE);
+  // z-geometry of the planes this block stages, uniform over the block: held
+  // in LDS instead of being loaded by every thread at every plane
+  __shared__ T zgeo_lds[3][kMaxZChunk + 3];
+  const int qmax = min(ke, g.nz - 1);
+  for (int e = tid; e <= qmax - ks; e += NT) {
+    const ZGeo<T> z = zgeo_raw<T>(g, ks + e);
+    zgeo_lds[0][e] = z.hzl;
+    zgeo_lds[1][e] = z.hzh;
+    zgeo_lds[2][e] = z.ivz;
+  }
   const cx<T> pcoef = port_coef_mode<T>(L.omega, MODE);
   const T w2 = (T)(L.omega * L.omega);
   const ColGeo<T> cg = col_geo<T>(g, ic, jc);
-  __syncthreads();  // material table ready
+  __syncthreads();  // material table and z-geometry ready
 
   PlaneRec<T> lo = plane_rec(mat, cg, inb ? load_cell_ids(g, i, j, ks - 1) : 0xFFFFFFFFu);
 
@@ -233,7 +246,6 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
   struct Pending {
     typename Op::Raw raw;
     CellIdsRaw ids;
-    ZGeo<T> z;
   };
   Pending pa, pb;
   Staged<T> sn;  // the next plane (staged one step ahead)
@@ -244,7 +256,6 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
 
   // Loads are unconditional, from a plane clamped into [0, min(ke, nz-1)];
   // process() applies the validity of the plane it stages.
-  const int qmax = min(ke, g.nz - 1);
   auto fetch = [&](int q, Pending& f) {
     const int qc = min(q, qmax);
     op.load(col + (int64_t)qc * plane, f.raw);
@@ -252,13 +263,13 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
       if (owner) op.load_own(col + (int64_t)qc * plane, f.raw);
     }
     f.ids = load_cell_ids_raw_inrange(g, il, jl, qc);
-    f.z = zgeo_raw<T>(g, qc);
   };
   auto process = [&](int q, Pending& f) {
     // planes above the chunk's last needed plane (or the grid) stage as ghosts
     const bool pin = q <= qmax;
     if (!(inb && pin)) op.zero(f.raw);
-    const ZGeo<T> z = pin ? f.z : ZGeo<T>{T(0), T(0), T(0)};
+    const ZGeo<T> z = pin ? ZGeo<T>{zgeo_lds[0][q - ks], zgeo_lds[1][q - ks], zgeo_lds[2][q - ks]}
+                          : ZGeo<T>{T(0), T(0), T(0)};
     const PlaneRec<T> hi = plane_rec(mat, cg, (inb && pin) ? decode_cell_ids(f.ids) : 0xFFFFFFFFu);
     const NodeCoef<T> nc = node_coef(cg, lo, hi, z.hzl, z.hzh, z.ivz, q, pcoef);
     lo = hi;
@@ -428,7 +439,7 @@ inline int launch_blocks(const StencilLaunch& L) { return L.nbx * L.nby * L.nbz;
 
 // Block shapes compiled into the library (whole wavefronts each).
 inline bool tile_supported(TileShape t) {
-  return t.zc >= 1 && ((t.tx == 64 && t.ty == 8) || (t.tx == 48 && t.ty == 8) ||
+  return t.zc >= 1 && t.zc <= kMaxZChunk && ((t.tx == 64 && t.ty == 8) || (t.tx == 48 && t.ty == 8) ||
                        (t.tx == 32 && t.ty == 8) || (t.tx == 32 && t.ty == 16));
 }
 

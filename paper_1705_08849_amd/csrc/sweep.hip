@@ -101,7 +101,7 @@ int zc_for(const fit_grid* g, int dtype, TileShape t) {
   const TileShape tt = tile_for(g, dtype);
   if (tt.tx == t.tx && tt.ty == t.ty) return tt.zc;
   const long nbx = (g->view.nx + t.tx - 3) / (t.tx - 2), nby = (g->view.ny + t.ty - 3) / (t.ty - 2);
-  int zc = g->view.nz;
+  int zc = std::min(g->view.nz, kMaxZChunk);
   while (zc > 8 && nbx * nby * ((g->view.nz + zc - 1) / zc) < 1024) zc = (zc + 1) / 2;
   return std::max(zc, 1);
 }

@@ -1,4 +1,5 @@
 // Tile-shape table, defaults and the on-device autotuner.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -36,7 +37,7 @@ TileShape default_tile(const GridView& g, int dtype) {
   }
   const long nbx = (g.nx + t.tx - 3) / (t.tx - 2), nby = (g.ny + t.ty - 3) / (t.ty - 2);
   const long cols = nbx * nby;
-  int zc = g.nz;
+  int zc = std::min(g.nz, kMaxZChunk);
   const long target = 1024;  // ~4 workgroups per CU on 256 CUs
   while (zc > 8 && cols * ((g.nz + zc - 1) / zc) < target) zc = (zc + 1) / 2;
   t.zc = zc < 1 ? 1 : zc;
@@ -93,7 +94,7 @@ extern "C" fit_status fit_tile_set(const fit_grid* g, int dtype, int tx, int ty,
   }
   TileShape t{tx, ty, zc};
   if (!tile_supported(t)) {
-    set_error("fit_tile_set: shape not compiled ((tx,ty) in {(64,8),(48,8),(32,8),(32,16)}, zc >= 1)");
+    set_error("fit_tile_set: shape not compiled ((tx,ty) in {(64,8),(48,8),(32,8),(32,16)}, 1 <= zc <= 128)");
     return FIT_E_INVALID;
   }
   record_tile(g->view, dtype, t, 0.0);
@@ -127,7 +128,7 @@ extern "C" fit_status fit_autotune(const fit_grid* g, int dtype, int scaling, do
   fit_status st = FIT_OK;
   for (TileShape base : shapes) {
     for (int z : zcs) {
-      if (z > g->view.nz && z != zcs[0]) continue;
+      if ((z > g->view.nz && z != zcs[0]) || z > kMaxZChunk) continue;
       TileShape t = base;
       t.zc = z;
       double us = 0;
