@@ -610,6 +610,22 @@ fit_status gemm(const GemmArgs& g, int64_t n_cols, hipStream_t s, int splits = 1
   const int64_t kpad = pad32(a.K);
   if (splits < 1) splits = 1;
   a.k_chunk = pad32((kpad + splits - 1) / splits);
+  // 3x3x3 convolutions with cin <= 64 take the LDS-staged kernel
+  if (a.gather == G_CONV3 && splits == 1 && a.cin <= 64 && a.ox == a.ix && a.oy == a.iy &&
+      a.M == (int64_t)a.ix * a.iy * a.iz && !a.up) {
+    const int64_t nb = (int64_t)((a.ix + kBrX - 1) / kBrX) * ((a.iy + kBrY - 1) / kBrY) * ((a.iz + kBrZ - 1) / kBrZ);
+    const dim3 grid((unsigned)nb, (unsigned)((n_cols + nt - 1) / nt), 1);
+    const int cm = a.cin <= 16 ? 16 : (a.cin <= 32 ? 32 : 64);
+    const int tok = prof_begin(s);
+#define CONV(NT, CM) \
+  if (nt == NT && cm == CM) hipLaunchKernelGGL((conv3_lds_kernel<NT, CM>), grid, dim3(256), 0, s, a);
+    CONV(16, 16) CONV(16, 32) CONV(16, 64) CONV(32, 16) CONV(32, 32) CONV(32, 64) CONV(64, 16) CONV(64, 32)
+    CONV(64, 64)
+#undef CONV
+    FIT_HIP(hipGetLastError());
+    prof_end(tok, s, "unet_conv3_lds_bf16");
+    return FIT_OK;
+  }
   const dim3 grid((unsigned)((a.M + 127) / 128), (unsigned)((n_cols + nt - 1) / nt), (unsigned)splits);
   const int tok = prof_begin(s);
   if (nt == 16)

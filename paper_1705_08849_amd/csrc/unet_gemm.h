@@ -64,6 +64,32 @@ struct GemmArgs {
   int64_t k_chunk;    // K per split (multiple of 32); gridDim.z splits
 };
 
+// Epilogue of one output element (row, n) of the GEMM.
+__device__ __forceinline__ void gemm_store(const GemmArgs& p, int64_t row, int n, float v) {
+  if (p.out == O_PART) {
+    p.o32[((int64_t)blockIdx.z * p.M + row) * p.N + n] = v;
+    return;
+  }
+  int64_t vox = row;
+  int ch = n;
+  if (p.up) {
+    const int tt = n / p.up_c;
+    ch = n % p.up_c;
+    const int ux = (int)(row % p.ox), uy = (int)((row / p.ox) % p.oy), uz = (int)(row / ((int64_t)p.ox * p.oy));
+    const int cx = 2 * ux + (tt & 1), cy = 2 * uy + ((tt >> 1) & 1), cz = 2 * uz + (tt >> 2);
+    vox = ((int64_t)cz * p.up_y + cy) * p.up_x + cx;
+  }
+  if (p.bias) v += p.bias[ch];
+  if (p.relu) v = v > 0.f ? v : 0.f;
+  const int64_t dst = vox * p.o_ld + ch;
+  if (p.out == O_BF16)
+    p.o16[dst] = (bf16)v;
+  else if (p.out == O_F32)
+    p.o32[dst] = v;
+  else
+    p.o32[dst] += v;
+}
+
 // Per-lane gather cursor over K: the current tap, the channel offset inside
 // the tap, and the tap's element offset (uniform over the lanes that share
 // the K position; the bounds test is per row).
@@ -177,38 +203,128 @@ __global__ void __launch_bounds__(256) igemm_kernel(GemmArgs p) {
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
       const int n = n0 + t * 16 + (lane & 15);
-      if (n >= p.N) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = m_tile + 16 * s + 4 * (lane >> 4) + r;
-        if (row >= p.M) continue;
-        float v = acc[s][t][r];
-        if (p.out == O_PART) {
-          p.o32[((int64_t)blockIdx.z * p.M + row) * p.N + n] = v;
-          continue;
-        }
-        int64_t vox = row;
-        int ch = n;
-        if (p.up) {
-          const int tt = n / p.up_c;
-          ch = n % p.up_c;
-          const int ux = (int)(row % p.ox), uy = (int)((row / p.ox) % p.oy),
-                    uz = (int)(row / ((int64_t)p.ox * p.oy));
-          const int cx = 2 * ux + (tt & 1), cy = 2 * uy + ((tt >> 1) & 1), cz = 2 * uz + (tt >> 2);
-          vox = ((int64_t)cz * p.up_y + cy) * p.up_x + cx;
-        }
-        if (p.bias) v += p.bias[ch];
-        if (p.relu) v = v > 0.f ? v : 0.f;
-        const int64_t dst = vox * p.o_ld + ch;
-        if (p.out == O_BF16)
-          p.o16[dst] = (bf16)v;
-        else if (p.out == O_F32)
-          p.o32[dst] = v;
-        else
-          p.o32[dst] += v;
+        if (row < p.M && n < p.N) gemm_store(p, row, n, acc[s][t][r]);
       }
     }
   }
 }
 
+// 3x3x3 convolution (G_CONV3, output dims = input dims) with the input
+// staged in LDS.  A workgroup outputs an 8 x 8 x 4 brick of voxels (256
+// rows); it first copies the brick's input with its one-voxel halo
+// (10 x 10 x 6 voxels, all cin <= CMAX channels, zeros outside the tensor)
+// into LDS, then reads every tap's A fragment from LDS instead of refetching
+// it through L1/L2 27 times.  Each wavefront owns 64 rows (one z-slice of the
+// brick, four 16-row subtiles), so a B fragment feeds four MFMAs.
+//
+// LDS layout: voxel h of the halo brick holds CMAX/8 16-byte chunks; chunk c
+// is stored at slot c ^ ((h / (8 / C8)) & (C8 - 1)).  Eight lanes reading the
+// same chunk of eight consecutive voxels then hit eight different 16-byte
+// slots of a 128-byte line (no bank conflict), whatever C8.
+// LDS: 600 * CMAX * 2 bytes (19.2 / 38.4 / 76.8 KB for CMAX = 16 / 32 / 64).
+constexpr int kBrX = 8, kBrY = 8, kBrZ = 4;
+constexpr int kHaX = kBrX + 2, kHaY = kBrY + 2, kHaZ = kBrZ + 2;
+constexpr int kHalo = kHaX * kHaY * kHaZ;
+
+template <int C8>
+__device__ __forceinline__ int conv_slot(int h, int c) {
+  constexpr int per_line = 8 / C8 > 0 ? 8 / C8 : 1;
+  return h * C8 + (c ^ ((h / per_line) & (C8 - 1)));
+}
+
+template <int NT, int CMAX>
+__global__ void __launch_bounds__(256) conv3_lds_kernel(GemmArgs p) {
+  constexpr int NS = NT / 16;
+  constexpr int MS = 4;
+  constexpr int C8 = CMAX / 8;
+  __shared__ bf16x8 tile[kHalo * C8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cin = p.cin, c8 = cin / 8;
+  const int nbx = (p.ix + kBrX - 1) / kBrX, nby = (p.iy + kBrY - 1) / kBrY;
+  const int b = blockIdx.x;
+  const int bx0 = (b % nbx) * kBrX, by0 = ((b / nbx) % nby) * kBrY, bz0 = (b / (nbx * nby)) * kBrZ;
+  // stage the halo brick: 16-byte chunks, zero outside the tensor and in
+  // the channel chunks past cin
+  for (int q = threadIdx.x; q < kHalo * C8; q += 256) {
+    const int cc = q % C8, h = q / C8;
+    const int hx = h % kHaX, hy = (h / kHaX) % kHaY, hz = h / (kHaX * kHaY);
+    const int x = bx0 + hx - 1, y = by0 + hy - 1, z = bz0 + hz - 1;
+    bf16x8 v;
+    if (cc < c8 && x >= 0 && y >= 0 && z >= 0 && x < p.ix && y < p.iy && z < p.iz) {
+      v = *reinterpret_cast<const bf16x8*>(p.a + (((int64_t)z * p.iy + y) * p.ix + x) * p.a_ld + 8 * cc);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (bf16)0.0f;
+    }
+    tile[conv_slot<C8>(h, cc)] = v;
+  }
+  __syncthreads();
+
+  const int n0 = blockIdx.y * NT;
+  const int kq = 8 * (lane >> 4);
+  // halo voxel of tap (-1, -1, -1) for each row of this lane
+  int hbase[MS];
+#pragma unroll
+  for (int s = 0; s < MS; ++s) {
+    const int rl = wave * 64 + 16 * s + (lane & 15);
+    const int lx = rl % kBrX, ly = (rl / kBrX) % kBrY, lz = rl / (kBrX * kBrY);
+    hbase[s] = (lz * kHaY + ly) * kHaX + lx;
+  }
+  floatx4 acc[MS][NS];
+#pragma unroll
+  for (int s = 0; s < MS; ++s)
+#pragma unroll
+    for (int t = 0; t < NS; ++t) acc[s][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int kpad = (int)((p.K + 31) / 32 * 32);
+  int tap = kq / cin, ci = kq % cin;
+  for (int kk = 0; kk < kpad; kk += 32) {
+    const int k = kk + kq;
+    const bool kv = k < p.K;
+    const int tc = tap < 26 ? tap : 26;  // past K the fragment is zero
+    const int dz = tc / 9, r9 = tc - 9 * dz, dy = r9 / 3, dx = r9 - 3 * dy;
+    const int hoff = (dz * kHaY + dy) * kHaX + dx;
+    bf16x8 av[MS];
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+      if (kv) {
+        av[s] = tile[conv_slot<C8>(hbase[s] + hoff, ci >> 3)];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[s][e] = (bf16)0.0f;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int n = n0 + t * 16 + (lane & 15);
+      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(p.b + (int64_t)n * p.ldb + k);
+#pragma unroll
+      for (int s = 0; s < MS; ++s)
+        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], bv, acc[s][t], 0, 0, 0);
+    }
+    ci += 32;
+    while (ci >= cin) {
+      ci -= cin;
+      ++tap;
+    }
+  }
+  // epilogue: the rows of the brick that lie inside the tensor
+#pragma unroll
+  for (int s = 0; s < MS; ++s) {
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int n = n0 + t * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rl = wave * 64 + 16 * s + 4 * (lane >> 4) + r;
+        const int x = bx0 + rl % kBrX, y = by0 + (rl / kBrX) % kBrY, z = bz0 + rl / (kBrX * kBrY);
+        if (x < p.ix && y < p.iy && z < p.iz && n < p.N)
+          gemm_store(p, ((int64_t)z * p.iy + y) * p.ix + x, n, acc[s][t][r]);
+      }
+    }
+  }
+}
 }  // namespace fit
