@@ -610,17 +610,18 @@ fit_status gemm(const GemmArgs& g, int64_t n_cols, hipStream_t s, int splits = 1
   const int64_t kpad = pad32(a.K);
   if (splits < 1) splits = 1;
   a.k_chunk = pad32((kpad + splits - 1) / splits);
-  // 3x3x3 convolutions with cin <= 64 take the LDS-staged kernel
-  if (a.gather == G_CONV3 && splits == 1 && a.cin <= 64 && a.ox == a.ix && a.oy == a.iy &&
+  // 3x3x3 convolutions with 8, 16, 32 or 64 input channels take the
+  // LDS-staged kernel
+  const bool lds_cin = a.cin == 8 || a.cin == 16 || a.cin == 32 || a.cin == 64;
+  if (a.gather == G_CONV3 && splits == 1 && lds_cin && a.K == 27LL * a.cin && a.ox == a.ix && a.oy == a.iy &&
       a.M == (int64_t)a.ix * a.iy * a.iz && !a.up) {
     const int64_t nb = (int64_t)((a.ix + kBrX - 1) / kBrX) * ((a.iy + kBrY - 1) / kBrY) * ((a.iz + kBrZ - 1) / kBrZ);
     const dim3 grid((unsigned)nb, (unsigned)((n_cols + nt - 1) / nt), 1);
-    const int cm = a.cin <= 16 ? 16 : (a.cin <= 32 ? 32 : 64);
     const int tok = prof_begin(s);
-#define CONV(NT, CM) \
-  if (nt == NT && cm == CM) hipLaunchKernelGGL((conv3_lds_kernel<NT, CM>), grid, dim3(256), 0, s, a);
-    CONV(16, 16) CONV(16, 32) CONV(16, 64) CONV(32, 16) CONV(32, 32) CONV(32, 64) CONV(64, 16) CONV(64, 32)
-    CONV(64, 64)
+#define CONV(NT, CI) \
+  if (nt == NT && a.cin == CI) hipLaunchKernelGGL((conv3_lds_kernel<NT, CI>), grid, dim3(256), 0, s, a);
+    CONV(16, 8) CONV(16, 16) CONV(16, 32) CONV(16, 64) CONV(32, 8) CONV(32, 16) CONV(32, 32) CONV(32, 64)
+    CONV(64, 8) CONV(64, 16) CONV(64, 32) CONV(64, 64)
 #undef CONV
     FIT_HIP(hipGetLastError());
     prof_end(tok, s, "unet_conv3_lds_bf16");

@@ -14,14 +14,15 @@
 // scatter the 8 children of a transposed 2x2x2 convolution, accumulate into
 // fp32 gradients, or write split-K partial sums.
 //
-// Tiling for CDNA4: a 256-thread workgroup computes 128 rows x NT columns;
-// each wavefront owns two 16-row subtiles and 2 x NT/16 accumulators of the
-// 16x16x32 bf16 MFMA, so each B fragment feeds two MFMAs.  Each lane loads
-// its 8 consecutive K values of A (one 16-byte load, since channel counts are
-// multiples of 8) and of B, so no LDS staging is needed: the 27-fold reuse of
-// an input voxel across taps is served by L1/L2.  The gather walks K with a
-// per-lane (tap, channel) cursor; a tap's element offset is one add, and the
-// row's bounds are three bit tests.
+// Tiling for CDNA4 (general kernel, igemm_kernel): a 256-thread workgroup
+// computes 128 rows x NT columns; each wavefront owns two 16-row subtiles and
+// 2 x NT/16 accumulators of the 16x16x32 bf16 MFMA, so each B fragment feeds
+// two MFMAs.  Each lane loads its 8 consecutive K values of A (one 16-byte
+// load, since channel counts are multiples of 8) and of B straight from
+// global memory.  The gather walks K with a per-lane (tap, channel) cursor; a
+// tap's element offset is one add, and the row's bounds are three bit tests.
+// 3x3x3 convolutions with 8, 16, 32 or 64 input channels, the bulk of the work,
+// use conv3_lds_kernel instead, which stages its input brick in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -64,24 +65,52 @@ struct GemmArgs {
   int64_t k_chunk;    // K per split (multiple of 32); gridDim.z splits
 };
 
-// Epilogue of one output element (row, n) of the GEMM.
-__device__ __forceinline__ void gemm_store(const GemmArgs& p, int64_t row, int n, float v) {
+// Epilogue.  An output element (row, n) goes to o16/o32[row_off + col.off]:
+// the row part and the column part are computed once per row and once per
+// column of a lane's accumulators, in 32-bit index arithmetic (M < 2^31).
+struct EpiCol {
+  int64_t off;  // column part of the destination offset
+  float bias;
+  bool ok;      // n < N
+};
+
+__device__ __forceinline__ EpiCol epi_col(const GemmArgs& p, int n) {
+  EpiCol c;
+  c.ok = n < p.N;
+  const int nn = c.ok ? n : 0;
   if (p.out == O_PART) {
-    p.o32[((int64_t)blockIdx.z * p.M + row) * p.N + n] = v;
+    c.off = nn;
+    c.bias = 0.f;
+    return c;
+  }
+  int ch = nn;
+  int64_t child = 0;
+  if (p.up) {  // column n = tt * up_c + ch goes to child tt of the row's voxel
+    const int tt = nn / p.up_c;
+    ch = nn - tt * p.up_c;
+    child = ((int64_t)(tt >> 2) * p.up_y + ((tt >> 1) & 1)) * p.up_x + (tt & 1);
+  }
+  c.off = child * p.o_ld + ch;
+  c.bias = p.bias ? p.bias[ch] : 0.f;
+  return c;
+}
+
+__device__ __forceinline__ int64_t epi_row(const GemmArgs& p, int64_t row) {
+  if (p.out == O_PART) return ((int64_t)blockIdx.z * p.M + row) * p.N;
+  if (!p.up) return row * p.o_ld;
+  const uint32_t r = (uint32_t)row, ox = (uint32_t)p.ox, oy = (uint32_t)p.oy;
+  const uint32_t t = r / ox, ux = r - t * ox, uz = t / oy, uy = t - uz * oy;
+  return (((int64_t)(2 * uz) * p.up_y + 2 * uy) * p.up_x + 2 * ux) * p.o_ld;
+}
+
+__device__ __forceinline__ void epi_put(const GemmArgs& p, int64_t roff, const EpiCol& c, float v) {
+  const int64_t dst = roff + c.off;
+  if (p.out == O_PART) {
+    p.o32[dst] = v;
     return;
   }
-  int64_t vox = row;
-  int ch = n;
-  if (p.up) {
-    const int tt = n / p.up_c;
-    ch = n % p.up_c;
-    const int ux = (int)(row % p.ox), uy = (int)((row / p.ox) % p.oy), uz = (int)(row / ((int64_t)p.ox * p.oy));
-    const int cx = 2 * ux + (tt & 1), cy = 2 * uy + ((tt >> 1) & 1), cz = 2 * uz + (tt >> 2);
-    vox = ((int64_t)cz * p.up_y + cy) * p.up_x + cx;
-  }
-  if (p.bias) v += p.bias[ch];
+  v += c.bias;
   if (p.relu) v = v > 0.f ? v : 0.f;
-  const int64_t dst = vox * p.o_ld + ch;
   if (p.out == O_BF16)
     p.o16[dst] = (bf16)v;
   else if (p.out == O_F32)
@@ -198,80 +227,126 @@ __global__ void __launch_bounds__(256) igemm_kernel(GemmArgs p) {
   }
 
   // epilogue: lane holds rows m_tile + 16 s + 4*(lane/16) + r, column n0 + 16 t + lane%16
+  EpiCol col[NS];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) col[t] = epi_col(p, n0 + t * 16 + (lane & 15));
 #pragma unroll
   for (int s = 0; s < MS; ++s) {
 #pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      const int n = n0 + t * 16 + (lane & 15);
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = m_tile + 16 * s + 4 * (lane >> 4) + r;
+      if (row >= p.M) continue;
+      const int64_t roff = epi_row(p, row);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m_tile + 16 * s + 4 * (lane >> 4) + r;
-        if (row < p.M && n < p.N) gemm_store(p, row, n, acc[s][t][r]);
-      }
+      for (int t = 0; t < NS; ++t)
+        if (col[t].ok) epi_put(p, roff, col[t], acc[s][t][r]);
     }
   }
 }
 
-// 3x3x3 convolution (G_CONV3, output dims = input dims) with the input
-// staged in LDS.  A workgroup outputs an 8 x 8 x 4 brick of voxels (256
-// rows); it first copies the brick's input with its one-voxel halo
-// (10 x 10 x 6 voxels, all cin <= CMAX channels, zeros outside the tensor)
-// into LDS, then reads every tap's A fragment from LDS instead of refetching
-// it through L1/L2 27 times.  Each wavefront owns 64 rows (one z-slice of the
-// brick, four 16-row subtiles), so a B fragment feeds four MFMAs.
+// 3x3x3 convolution (G_CONV3, output dims = input dims, CIN in {8, 16, 32,
+// 64} input channels) with the input staged in LDS.  A workgroup outputs an
+// 8 x 8 x 4 brick of voxels (256 rows); it first copies the brick's input
+// with its one-voxel halo (10 x 10 x 6 voxels, zeros outside the tensor) into
+// LDS, then reads every tap's A fragment from LDS instead of refetching it
+// through L1/L2 27 times.  Each wavefront owns 64 rows (one z-slice of the
+// brick, four 16-row subtiles), so a B fragment feeds four MFMAs; B is read
+// through a ring of registers several K steps ahead.
 //
-// LDS layout: voxel h of the halo brick holds CMAX/8 16-byte chunks; chunk c
-// is stored at slot c ^ ((h / (8 / C8)) & (C8 - 1)).  Eight lanes reading the
-// same chunk of eight consecutive voxels then hit eight different 16-byte
-// slots of a 128-byte line (no bank conflict), whatever C8.
-// LDS: 600 * CMAX * 2 bytes (19.2 / 38.4 / 76.8 KB for CMAX = 16 / 32 / 64).
+// LDS layout: voxel h of the halo brick holds C8 = CIN/8 16-byte chunks;
+// chunk c is stored at slot c ^ ((h / (8 / C8)) & (C8 - 1)).  Eight lanes
+// reading the same chunk of eight consecutive voxels then hit eight different
+// 16-byte slots of a 128-byte line (no bank conflict), whatever C8.
+// LDS: 600 * CIN * 2 bytes (9.6 / 19.2 / 38.4 / 76.8 KB).
 constexpr int kBrX = 8, kBrY = 8, kBrZ = 4;
 constexpr int kHaX = kBrX + 2, kHaY = kBrY + 2, kHaZ = kBrZ + 2;
 constexpr int kHalo = kHaX * kHaY * kHaZ;
 
 template <int C8>
-__device__ __forceinline__ int conv_slot(int h, int c) {
-  constexpr int per_line = 8 / C8 > 0 ? 8 / C8 : 1;
-  return h * C8 + (c ^ ((h / per_line) & (C8 - 1)));
+__device__ __forceinline__ int conv_slot(unsigned h, unsigned c) {
+  constexpr unsigned per_line = 8 / C8 > 0 ? 8 / C8 : 1;
+  return (int)(h * C8 + (c ^ ((h / per_line) & (C8 - 1))));
 }
 
-template <int NT, int CMAX>
+template <int NT, int CIN>
 __global__ void __launch_bounds__(256) conv3_lds_kernel(GemmArgs p) {
   constexpr int NS = NT / 16;
   constexpr int MS = 4;
-  constexpr int C8 = CMAX / 8;
-  __shared__ bf16x8 tile[kHalo * C8];
+  constexpr int C8 = CIN / 8;
+  constexpr int TOT = kHalo * C8;            // 16-byte chunks to stage
+  constexpr int NIT = (TOT + 255) / 256;     // chunks per thread
+  constexpr int NB = (NIT + 7) / 8;          // batches of at most 8 loads in flight
+  constexpr int BATCH = (NIT + NB - 1) / NB;
+  __shared__ bf16x8 tile[TOT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int cin = p.cin, c8 = cin / 8;
   const int nbx = (p.ix + kBrX - 1) / kBrX, nby = (p.iy + kBrY - 1) / kBrY;
   const int b = blockIdx.x;
   const int bx0 = (b % nbx) * kBrX, by0 = ((b / nbx) % nby) * kBrY, bz0 = (b / (nbx * nby)) * kBrZ;
-  // stage the halo brick: 16-byte chunks, zero outside the tensor and in
-  // the channel chunks past cin
-  for (int q = threadIdx.x; q < kHalo * C8; q += 256) {
-    const int cc = q % C8, h = q / C8;
-    const int hx = h % kHaX, hy = (h / kHaX) % kHaY, hz = h / (kHaX * kHaY);
-    const int x = bx0 + hx - 1, y = by0 + hy - 1, z = bz0 + hz - 1;
-    bf16x8 v;
-    if (cc < c8 && x >= 0 && y >= 0 && z >= 0 && x < p.ix && y < p.iy && z < p.iz) {
-      v = *reinterpret_cast<const bf16x8*>(p.a + (((int64_t)z * p.iy + y) * p.ix + x) * p.a_ld + 8 * cc);
-    } else {
+  // B fragments: a ring of D slots filled ahead of use; the first loads are
+  // issued before the halo staging so that their latency overlaps it
+  constexpr int K = 27 * CIN;
+  constexpr int NFULL = K / 32;
+  constexpr bool PART = (K % 32) != 0;
+  constexpr int NSTEP = NFULL + (PART ? 1 : 0);
+  constexpr int LAST = (NSTEP - 1) * 32;
+  constexpr int DW = NS >= 4 ? 2 : 4;  // ring depth (wide tiles already have NS loads per step)
+  constexpr int D = NSTEP < DW ? NSTEP : DW;
+  const int n0 = blockIdx.y * NT;
+  const int kq = 8 * (lane >> 4);
+  const bf16* brow[NS];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (bf16)0.0f;
+  for (int t = 0; t < NS; ++t) brow[t] = p.b + (int64_t)(n0 + t * 16 + (lane & 15)) * p.ldb + kq;
+  auto load_b = [&](bf16x8(&dst)[NS], int kk) {
+    const int kc = kk < LAST ? kk : LAST;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) dst[t] = *reinterpret_cast<const bf16x8*>(brow[t] + kc);
+  };
+  bf16x8 bq[D][NS];
+#pragma unroll
+  for (int i = 0; i < D; ++i) load_b(bq[i], i * 32);
+
+  // stage the halo brick: every load is issued from a clamped (in-range)
+  // address before any is written to LDS; voxels outside the tensor are
+  // replaced by zeros
+  for (int q0 = 0; q0 < NB * BATCH * 256; q0 += BATCH * 256) {
+    bf16x8 v[BATCH];
+    bool in[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int q = q0 + u * 256 + (int)threadIdx.x;
+      const int qq = q < TOT ? q : TOT - 1;
+      const int cc = qq % C8, h = qq / C8;
+      const int hx = h % kHaX, hy = (h / kHaX) % kHaY, hz = h / (kHaX * kHaY);
+      const int x = bx0 + hx - 1, y = by0 + hy - 1, z = bz0 + hz - 1;
+      in[u] = x >= 0 && y >= 0 && z >= 0 && x < p.ix && y < p.iy && z < p.iz;
+      const int xc = x < 0 ? 0 : (x < p.ix ? x : p.ix - 1);
+      const int yc = y < 0 ? 0 : (y < p.iy ? y : p.iy - 1);
+      const int zc = z < 0 ? 0 : (z < p.iz ? z : p.iz - 1);
+      v[u] = *reinterpret_cast<const bf16x8*>(p.a + (((int64_t)zc * p.iy + yc) * p.ix + xc) * p.a_ld + 8 * cc);
     }
-    tile[conv_slot<C8>(h, cc)] = v;
+    // threads past the end rewrite chunk TOT - 1 with the value its owner
+    // writes, which keeps the stores unconditional
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+      const int q = q0 + u * 256 + (int)threadIdx.x;
+      const int qq = q < TOT ? q : TOT - 1;
+      bf16x8 w = v[u];
+      if (!in[u]) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[e] = (bf16)0.0f;
+      }
+      tile[conv_slot<C8>(qq / C8, qq % C8)] = w;
+    }
   }
   __syncthreads();
 
-  const int n0 = blockIdx.y * NT;
-  const int kq = 8 * (lane >> 4);
   // halo voxel of tap (-1, -1, -1) for each row of this lane
-  int hbase[MS];
+  unsigned hbase[MS];
 #pragma unroll
   for (int s = 0; s < MS; ++s) {
     const int rl = wave * 64 + 16 * s + (lane & 15);
     const int lx = rl % kBrX, ly = (rl / kBrX) % kBrY, lz = rl / (kBrX * kBrY);
-    hbase[s] = (lz * kHaY + ly) * kHaX + lx;
+    hbase[s] = (unsigned)((lz * kHaY + ly) * kHaX + lx);
   }
   floatx4 acc[MS][NS];
 #pragma unroll
@@ -279,51 +354,60 @@ __global__ void __launch_bounds__(256) conv3_lds_kernel(GemmArgs p) {
 #pragma unroll
     for (int t = 0; t < NS; ++t) acc[s][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  const int kpad = (int)((p.K + 31) / 32 * 32);
-  int tap = kq / cin, ci = kq % cin;
-  for (int kk = 0; kk < kpad; kk += 32) {
-    const int k = kk + kq;
-    const bool kv = k < p.K;
-    const int tc = tap < 26 ? tap : 26;  // past K the fragment is zero
-    const int dz = tc / 9, r9 = tc - 9 * dz, dy = r9 / 3, dx = r9 - 3 * dy;
-    const int hoff = (dz * kHaY + dy) * kHaX + dx;
+  // K = 27 * CIN runs in NFULL full steps of 32 and, for CIN = 8 or 16, a
+  // final partial step whose lanes past K read a valid tap and are zeroed.
+  auto step = [&](int kk, const bf16x8(&bc)[NS], bool partial) {
+    int kc = kk + kq;
+    bool kv = true;
+    if (partial) {
+      kv = kc < K;
+      kc = kv ? kc : K - 8;
+    }
+    const unsigned tap = (unsigned)kc / CIN, ci = (unsigned)kc % CIN;
+    const unsigned dz = tap / 9, r9 = tap - 9 * dz, dy = r9 / 3, dx = r9 - 3 * dy;
+    const unsigned hoff = (dz * kHaY + dy) * kHaX + dx;
     bf16x8 av[MS];
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
-      if (kv) {
-        av[s] = tile[conv_slot<C8>(hbase[s] + hoff, ci >> 3)];
-      } else {
+      av[s] = tile[conv_slot<C8>(hbase[s] + hoff, ci >> 3)];
+      if (partial && !kv) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) av[s][e] = (bf16)0.0f;
       }
     }
 #pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      const int n = n0 + t * 16 + (lane & 15);
-      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(p.b + (int64_t)n * p.ldb + k);
+    for (int t = 0; t < NS; ++t)
 #pragma unroll
       for (int s = 0; s < MS; ++s)
-        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], bv, acc[s][t], 0, 0, 0);
-    }
-    ci += 32;
-    while (ci >= cin) {
-      ci -= cin;
-      ++tap;
+        acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], bc[t], acc[s][t], 0, 0, 0);
+  };
+  // groups of D steps; slot i of the ring serves steps i, i + D, ...; a
+  // slot is refilled right after its step, D - 1 steps before it is needed
+  int st = 0;
+  for (; st + D <= NSTEP; st += D) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      step((st + i) * 32, bq[i], PART && st + i == NSTEP - 1);
+      load_b(bq[i], (st + i + D) * 32);
     }
   }
+#pragma unroll
+  for (int i = 0; i < NSTEP % D; ++i) step((st + i) * 32, bq[i], PART && st + i == NSTEP - 1);
   // epilogue: the rows of the brick that lie inside the tensor
+  EpiCol col[NS];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) col[t] = epi_col(p, n0 + t * 16 + (lane & 15));
 #pragma unroll
   for (int s = 0; s < MS; ++s) {
 #pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      const int n = n0 + t * 16 + (lane & 15);
+    for (int r = 0; r < 4; ++r) {
+      const int rl = wave * 64 + 16 * s + 4 * (lane >> 4) + r;
+      const int x = bx0 + rl % kBrX, y = by0 + (rl / kBrX) % kBrY, z = bz0 + rl / (kBrX * kBrY);
+      if (x >= p.ix || y >= p.iy || z >= p.iz) continue;
+      const int64_t roff = epi_row(p, ((int64_t)z * p.iy + y) * p.ix + x);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rl = wave * 64 + 16 * s + 4 * (lane >> 4) + r;
-        const int x = bx0 + rl % kBrX, y = by0 + (rl / kBrX) % kBrY, z = bz0 + rl / (kBrX * kBrY);
-        if (x < p.ix && y < p.iy && z < p.iz && n < p.N)
-          gemm_store(p, ((int64_t)z * p.iy + y) * p.ix + x, n, acc[s][t][r]);
-      }
+      for (int t = 0; t < NS; ++t)
+        if (col[t].ok) epi_put(p, roff, col[t], acc[s][t][r]);
     }
   }
 }
