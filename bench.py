@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 METRIC = "freq-points solved/sec at 1e-8 rel. residual; matvec GB/s vs HBM peak"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pcocg_step1_c128.json")
+# tile table for the bench grid, written by `bench.py --autotune --save-tune`
+TUNE_FILE = os.path.join(ROOT, "paper_1705_08849_amd", "tune_gfx950.json")
 KERNEL_SOURCES = ["paper_1705_08849_amd/csrc/stencil.h", "paper_1705_08849_amd/csrc/krylov.h",
                   "paper_1705_08849_amd/csrc/fit_internal.h", "paper_1705_08849_amd/csrc/reduce.h"]
 
@@ -40,9 +42,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(alg_bytes):
+def measured_traffic(tile):
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    rocprofv3 counter summary, if it was taken on the current kernel source
+    and with the tile this run uses."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -50,7 +53,30 @@ def measured_traffic(alg_bytes):
         return None
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
+    if tile is not None and t.get("tile") is not None and list(t["tile"]) != list(tile):
+        return None
     return t.get("bytes_per_launch")
+
+
+def bench_tile(fit, g, dev, omega, args):
+    """The tile the bench's grid runs with: the committed tile table's entry
+    for its node dimensions (so that repeated runs and the counter passes use
+    the same tile), or a fresh autotune with --autotune or when the table has
+    no entry; --no-autotune keeps the library's default shape."""
+    if args.no_autotune:
+        return None
+    nx, ny, nz = dev.nodes
+    if not args.autotune and os.path.exists(TUNE_FILE):
+        with open(TUNE_FILE) as f:
+            table = json.load(f)
+        for e in table.get("entries", []):
+            if (e["nx"], e["ny"], e["nz"], e["dtype"]) == (nx, ny, nz, fit.C128):
+                fit.tune_load(TUNE_FILE)
+                return (e["tx"], e["ty"], e["zc"])
+    tile, _ = g.autotune("c128", "none", omega, reps=20)
+    if args.save_tune:
+        fit.tune_save(TUNE_FILE)
+    return tile
 
 
 def counter_sample(args):
@@ -67,8 +93,7 @@ def counter_sample(args):
     dev = D.plain_device_128(2)
     omega = 2 * np.pi * D.log_uniform_frequency(2)
     g = fit.Grid(dev)
-    if not args.no_autotune:
-        g.autotune("c128", "none", omega, reps=5)
+    tile = bench_tile(fit, g, dev, omega, args)
     src = torch.from_numpy(D.port_source(dev, 0)).to("cuda:0")
     g.solve(omega, src, tol=1e-8, solver="cocg", max_iters=40, raise_on_error=False)
     xr = torch.randn(dev.n_edges * 2, dtype=torch.float64, device="cuda:0")
@@ -76,7 +101,7 @@ def counter_sample(args):
     for _ in range(3):
         torch.neg(xr, out=yr)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_each_way": xr.numel() * 8}), flush=True)
+    print(json.dumps({"copy_bytes_each_way": xr.numel() * 8, "tile": tile}), flush=True)
 
 
 def _counter_rows(path):
@@ -85,10 +110,25 @@ def _counter_rows(path):
         return list(csv.DictReader(f))
 
 
-def ingest_counters(fetch_csv, write_csv, copy_bytes, commands):
+def _counter_run_info(log_path):
+    """The JSON line that a `--counters` run prints: the calibration copy's
+    bytes each way and the tile the run used."""
+    with open(log_path) as f:
+        for line in f:
+            if line.startswith("{") and "copy_bytes_each_way" in line:
+                return json.loads(line)
+    raise SystemExit(f"{log_path}: no line from a --counters run")
+
+
+def ingest_counters(fetch_csv, write_csv, fetch_log, write_log, commands):
     """Turn the two rocprofv3 counter CSVs of `--counters` into the per-launch
     HBM traffic of the fused COCG step-1 kernel, each counter scaled by what
-    it reads for the copy-shaped calibration kernel."""
+    it reads for the copy-shaped calibration kernel.  Both runs must have
+    used the same tile; it is recorded with the result."""
+    info_f, info_w = _counter_run_info(fetch_log), _counter_run_info(write_log)
+    if info_f != info_w:
+        raise SystemExit(f"the two counter runs differ: {info_f} vs {info_w}")
+    copy_bytes = int(info_f["copy_bytes_each_way"])
     def per_kernel(rows, counter):
         acc = {}
         for r in rows:
@@ -110,7 +150,7 @@ def ingest_counters(fetch_csv, write_csv, copy_bytes, commands):
         return sum(vals) / len(vals), len(vals)
 
     out = {"kernel": "pcocg_step1_c128", "kernel_source_hash": kernel_source_hash(),
-           "commands": commands}
+           "tile": info_f.get("tile"), "commands": commands}
     for counter, path, key in (("FETCH_SIZE", fetch_csv, "fetch"), ("WRITE_SIZE", write_csv, "write")):
         acc = per_kernel(_counter_rows(path), counter)
         kib, n = pick(acc, "stencil_kernel<double", "OpCocgPX")
@@ -276,18 +316,24 @@ def main():
     ap.add_argument("--solver", default="cocg")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run with the library's default tile shape")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the bench grid instead of reading the committed tile table")
+    ap.add_argument("--save-tune", action="store_true",
+                    help="with --autotune: write the tile table to the committed file")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the secondary rows (batched sweep, learned preconditioner)")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short sample profiled by the HBM-counter passes")
-    ap.add_argument("--ingest", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_BYTES"),
-                    help="write the measured per-launch traffic from two counter CSVs")
+    ap.add_argument("--ingest", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_LOG", "WRITE_LOG"),
+                    help="write the measured per-launch traffic from two counter CSVs and the "
+                         "stdout of the two --counters runs")
     args = ap.parse_args()
     if args.ingest:
         cmds = ["rocprofv3 --pmc FETCH_SIZE -f csv -- python3 bench.py --counters",
                 "rocprofv3 --pmc WRITE_SIZE -f csv -- python3 bench.py --counters"]
-        ingest_counters(args.ingest[0], args.ingest[1], int(args.ingest[2]), cmds)
+        ingest_counters(*args.ingest, cmds)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -318,9 +364,7 @@ def main():
     t_create = time.perf_counter() - t0
     src = torch.from_numpy(src_np).to("cuda:0")
     x = torch.empty_like(src)
-    tile = None
-    if not args.no_autotune:
-        tile, _ = g.autotune("c128", "none", omega, reps=5)
+    tile = bench_tile(fit, g, dev, omega, args)
 
     # plain operator bandwidth (the metric's second part)
     xv = torch.randn(dev.n_edges, dtype=torch.complex128, device="cuda:0")
@@ -374,7 +418,7 @@ def main():
         achieved = alg / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(alg), "kernel": kname,
+                "traffic": measured_traffic(tile), "kernel": kname,
                 "avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": alg,
                 "launches": launches}
     share = {k: round(v[1] / 1e3 / elapsed, 3) for k, v in sorted(stats.items())}

@@ -263,8 +263,11 @@ fit_status fit_tile_set(const struct fit_grid *g, int dtype, int tx, int ty, int
 
 /* Time every compiled (TX, TY) with a range of ZC on g (operator in `dtype`
  * and `scaling` at omega, `reps` timed launches each, HIP events on `stream`),
- * record the fastest in the table and report it.  best_us: mean kernel time of
- * the winner.  Synchronous; allocates two scratch vectors. */
+ * record the fastest in the table and report it.  Candidates are timed in a
+ * fixed order ((64,8), (48,8), (32,8), (32,16), each with ascending zc) and a
+ * later one replaces the best so far only if it is more than 2 % faster, so
+ * near-ties resolve the same way from run to run.  best_us: mean kernel time
+ * of the winner.  Synchronous; allocates two scratch vectors. */
 fit_status fit_autotune(const struct fit_grid *g, int dtype, int scaling, double omega, int reps,
                         void *stream, int32_t *tx, int32_t *ty, int32_t *zc, double *best_us);
 

@@ -135,7 +135,10 @@ extern "C" fit_status fit_autotune(const fit_grid* g, int dtype, int scaling, do
       st = dtype == FIT_C128 ? time_shape<double>(g, t, scaling, omega, reps, x, y, s, &us)
                              : time_shape<float>(g, t, scaling, omega, reps, x, y, s, &us);
       if (st != FIT_OK) break;
-      if (us < best_t) {
+      // a later candidate must beat the best so far by more than the timing
+      // noise (2 %), so near-ties go to the earlier candidate and repeated
+      // runs pick the same tile
+      if (us < 0.98 * best_t) {
         best_t = us;
         best = t;
       }

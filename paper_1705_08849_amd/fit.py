@@ -8,6 +8,7 @@ shared library is missing the binding raises; there is no fallback.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from pathlib import Path
 from typing import Optional, Sequence
 
@@ -86,6 +87,16 @@ def profile_stop():
     buf = (KernelStat * 64)()
     check(lib().fit_profile_stop(buf, 64, C.byref(n)), "fit_profile_stop")
     return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(n.value, 64))}
+
+
+def tune_save(path: str):
+    """Write the process-wide tile table (fit_tune_save)."""
+    check(lib().fit_tune_save(os.fsencode(path)), "fit_tune_save")
+
+
+def tune_load(path: str):
+    """Merge a saved tile table into the process-wide one (fit_tune_load)."""
+    check(lib().fit_tune_load(os.fsencode(path)), "fit_tune_load")
 
 
 class PrecondCfg(C.Structure):
