@@ -373,6 +373,7 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
   T* z = V.s;
   T* mdiag = V.t;
   const int64_t nbn = nb;
+  const OtfShape otf = otf_shape(c.g->view, c.max_blocks);
   if (pre) {
     hipLaunchKernelGGL(mass_inverse_kernel<T>, dim3((unsigned)pw_blocks(c.g->view.np)), dim3(256),
                        0, c.s, c.g->view, c.omega, mdiag);
@@ -396,18 +397,18 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
     }
     const int tok = prof_begin(c.s);
     if (pre) {
-      hipLaunchKernelGGL(pcocg_rupdate_kernel<T>, dim3((unsigned)nbn), dim3(256), 0, c.s, ne, V.r,
-                         q, mdiag, c.cst, c.part);
+      hipLaunchKernelGGL((pcocg_rupdate_otf_kernel<T, kOtfZc>), dim3((unsigned)otf.blocks), dim3(256),
+                         0, c.s, c.g->view, c.omega, V.r, q, c.cst, c.part);
     } else {
       hipLaunchKernelGGL(cocg_update_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, V.x, V.r,
                          p_new, q, ne, c.cst, c.part, c.cnt);
     }
     FIT_HIP(hipGetLastError());
     prof_end(tok, c.s, sizeof(T) == 8 ? "cocg_update_c128" : "cocg_update_c64");
-    FIT_HIP(launch_finish<3>(c.part, (int)(pre ? nbn : nb), CocgFinish{c.cst}, c.s));
+    FIT_HIP(launch_finish<3>(c.part, (int)(pre ? otf.blocks : nb), CocgFinish{c.cst}, c.s));
     return FIT_OK;
   };
-  const double per_iter_bytes = node_bytes(c.g, 10, sizeof(T));
+  const double per_iter_bytes = node_bytes(c.g, pre ? 9 : 10, sizeof(T));
   if (check_every <= 0) check_every = 2 * std::max(1, std::min(100, (int)(4e8 / (double)ne)));
   if (check_every & 1) ++check_every;
   hipGraphExec_t gexec = nullptr;

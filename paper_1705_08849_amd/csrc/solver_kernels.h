@@ -478,74 +478,126 @@ __global__ void __launch_bounds__(256)
   pcocg_update_body<T, INIT>(n, x, r, z, p, q, m, st, part, blockIdx.x, gridDim.x);
 }
 
-// The same update for several systems in one launch: item s owns the blocks
-// [block0, block0 + nblk).
+// The same step with the preconditioner diagonal recomputed instead of read:
+// m = -omega^2 / d_e from the cell ids, the material table and the 1-D
+// widths, by the same expression the fused operator kernel uses for
+// p = m .* r + beta p (OpCocgPX::input_coef), so both kernels apply the same
+// M.  This drops the stored m vector (one of four vector passes) from the
+// kernel.  Layout: a thread owns one node column (i, j) and marches up a
+// chunk of `zc` planes, reusing the column geometry and the lower plane's
+// cell record; consecutive threads are consecutive columns, so every plane's
+// loads and stores are contiguous.  Blocks loop over (column block, z-chunk)
+// pairs; block b writes partial b.
+template <class T, int ZC>
+__device__ __forceinline__ void pcocg_rupdate_otf_body(const GridView& g, double omega, T* r, const T* q,
+                                                       CgState* st, double* part, int bid, int nblk) {
+  __shared__ MatLds<T> mat;
+  __shared__ double lds[3 * 4];
+  fill_mat_mode<T>(mat, g.mats, omega, MODE_D);
+  __syncthreads();
+  const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
+  const cx<T> pc = port_coef_mode<T>(omega, MODE_D);
+  const T w2 = (T)(omega * omega);
+  const int ncol = g.nx * g.ny;
+  const int nbxy = (ncol + 255) / 256, nbz = (g.nz + ZC - 1) / ZC;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int ch = bid; ch < nbxy * nbz; ch += nblk) {
+    const int c = (ch % nbxy) * 256 + (int)threadIdx.x;
+    if (c >= ncol) continue;
+    const int k0 = (ch / nbxy) * ZC, k1 = min(k0 + ZC, g.nz);
+    const int j = c / g.nx, i = c - j * g.nx;
+    // every load of the chunk is issued before any is used (planes past the
+    // grid re-read the last plane and are not stored)
+    cx<T> rv[ZC][3], qv[ZC][3];
+    CellIdsRaw ids[ZC + 1];
+    ids[0] = load_cell_ids_raw_inrange(g, i, j, k0 - 1);
+#pragma unroll
+    for (int u = 0; u < ZC; ++u) {
+      const int k = min(k0 + u, k1 - 1);
+      const int64_t n = (int64_t)k * ncol + c;
+      ids[u + 1] = load_cell_ids_raw_inrange(g, i, j, k);
+#pragma unroll
+      for (int w = 0; w < 3; ++w) {
+        rv[u][w] = ldc(r, 3 * n + w);
+        qv[u][w] = ldc(q, 3 * n + w);
+      }
+    }
+    const ColGeo<T> cg = col_geo<T>(g, i, j);
+    PlaneRec<T> lo = plane_rec(mat, cg, decode_cell_ids(ids[0]));
+#pragma unroll
+    for (int u = 0; u < ZC; ++u) {
+      const int k = k0 + u;
+      if (k >= k1) break;
+      const PlaneRec<T> hi = plane_rec(mat, cg, decode_cell_ids(ids[u + 1]));
+      const ZGeo<T> z = zgeo_raw<T>(g, k);
+      const NodeCoef<T> nc = node_coef(cg, lo, hi, z.hzl, z.hzh, z.ivz, k, pc);
+      lo = hi;
+      const int64_t n = (int64_t)k * ncol + c;
+#pragma unroll
+      for (int w = 0; w < 3; ++w) {
+        const cx<T> d = nc.e[w];
+        const bool fr = (nc.mask >> w) & 1u;
+        const T a2 = fr ? d.re * d.re + d.im * d.im : T(1);
+        const T f = fr ? -w2 / a2 : T(0);
+        const cx<T> m{f * d.re, -f * d.im};
+        const cx<T> rn = rv[u][w] - al * qv[u][w];
+        stc(r, 3 * n + w, rn);
+        const cx<T> zv = m * rn;
+        const double rr = rn.re, ri = rn.im, zr = zv.re, zi = zv.im;
+        acc[0] += rr * zr - ri * zi;
+        acc[1] += rr * zi + ri * zr;
+        acc[2] += rr * rr + ri * ri;
+      }
+    }
+  }
+  block_partial_at<3>(acc, part, lds, bid);
+}
+
+template <class T, int ZC>
+__global__ void __launch_bounds__(256)
+    pcocg_rupdate_otf_kernel(GridView g, double omega, T* r, const T* q, CgState* st, double* part) {
+  if (*(volatile int*)&st->done != kRunning) return;
+  pcocg_rupdate_otf_body<T, ZC>(g, omega, r, q, st, part, blockIdx.x, gridDim.x);
+}
+
+// The same for several systems (possibly on different grids) in one launch:
+// item s owns the blocks [block0, block0 + nblk).
 template <class T>
-struct PcocgItem {
-  int64_t n;
-  T *x, *r, *z;
-  const T *p, *q, *m;
+struct OtfItem {
+  GridView g;
+  double omega;
+  T* r;
+  const T* q;
   CgState* st;
   double* part;
   int block0, nblk;
 };
 
-template <class T, bool INIT>
+template <class T, int ZC>
 __global__ void __launch_bounds__(256)
-    pcocg_update_multi_kernel(const PcocgItem<T>* __restrict__ items, int nitems) {
+    pcocg_rupdate_otf_multi_kernel(const OtfItem<T>* __restrict__ items, int nitems) {
   const int b = blockIdx.x;
   int lo = 0, hi = nitems - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (items[mid].block0 <= b) lo = mid; else hi = mid - 1;
   }
-  const PcocgItem<T> it = items[lo];
+  const OtfItem<T>& it = items[lo];
   if (*(volatile int*)&it.st->done != kRunning) return;
-  pcocg_update_body<T, INIT>(it.n, it.x, it.r, it.z, it.p, it.q, it.m, it.st, it.part,
-                             b - it.block0, it.nblk);
+  pcocg_rupdate_otf_body<T, ZC>(it.g, it.omega, it.r, it.q, it.st, it.part, b - it.block0, it.nblk);
 }
 
-// Streaming half of the fused mass-preconditioned COCG iteration (after
-// OpCocgPX): r -= alpha q, and r^T (m .* r), ||r||^2 (z = m .* r is not
-// stored: the next operator launch recomputes m).
-template <class T>
-__device__ __forceinline__ void pcocg_rupdate_body(int64_t n, T* r, const T* q, const T* m, CgState* st,
-                                                   double* part, int bid, int nblk) {
-  __shared__ double lds[3 * 4];
-  const cx<T> al{(T)st->alpha.re, (T)st->alpha.im};
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int64_t e = (int64_t)bid * blockDim.x + threadIdx.x; e < n; e += (int64_t)nblk * blockDim.x) {
-    const cx<T> rv = ldc(r, e) - al * ldc(q, e);
-    stc(r, e, rv);
-    const cx<T> zv = ldc(m, e) * rv;
-    const double rr = rv.re, ri = rv.im, zr = zv.re, zi = zv.im;
-    acc[0] += rr * zr - ri * zi;
-    acc[1] += rr * zi + ri * zr;
-    acc[2] += rr * rr + ri * ri;
-  }
-  block_partial_at<3>(acc, part, lds, bid);
-}
-
-template <class T>
-__global__ void __launch_bounds__(256)
-    pcocg_rupdate_kernel(int64_t n, T* r, const T* q, const T* m, CgState* st, double* part) {
-  if (*(volatile int*)&st->done != kRunning) return;
-  pcocg_rupdate_body<T>(n, r, q, m, st, part, blockIdx.x, gridDim.x);
-}
-
-// The same for several systems in one launch (PcocgItem: r, q, m, st, part).
-template <class T>
-__global__ void __launch_bounds__(256)
-    pcocg_rupdate_multi_kernel(const PcocgItem<T>* __restrict__ items, int nitems) {
-  const int b = blockIdx.x;
-  int lo = 0, hi = nitems - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (items[mid].block0 <= b) lo = mid; else hi = mid - 1;
-  }
-  const PcocgItem<T> it = items[lo];
-  if (*(volatile int*)&it.st->done != kRunning) return;
-  pcocg_rupdate_body<T>(it.n, it.r, it.q, it.m, it.st, it.part, b - it.block0, it.nblk);
+// Launch shape of pcocg_rupdate_otf_kernel: z-chunk and block count (at
+// most max_blocks partials).
+struct OtfShape {
+  int zc, blocks;
+};
+constexpr int kOtfZc = 4;
+inline OtfShape otf_shape(const GridView& g, int max_blocks) {
+  const int zc = kOtfZc;
+  const int64_t nbxy = ((int64_t)g.nx * g.ny + 255) / 256, nbz = (g.nz + zc - 1) / zc;
+  const int64_t b = nbxy * nbz;
+  return OtfShape{zc, (int)(b < max_blocks ? b : max_blocks)};
 }
 
 // The solution update still pending after the last fused step.

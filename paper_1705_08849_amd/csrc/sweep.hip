@@ -165,7 +165,7 @@ template <class T>
 struct Tables {
   MultiItem<OpCocgPX<T>>* stencil[2] = {nullptr, nullptr};  // by parity
   FinishItem<OpFinish<OpCocgPX<T>>>* fin1[2] = {nullptr, nullptr};
-  PcocgItem<T>* upd[2] = {nullptr, nullptr};
+  OtfItem<T>* upd[2] = {nullptr, nullptr};
   FinishItem<CocgFinish>* fin2 = nullptr;
   int n = 0, stencil_blocks = 0, upd_blocks = 0;
   TileShape shape{32, 8, 8};
@@ -183,7 +183,7 @@ fit_status build_tables(std::vector<Sys*>& act, Tables<T>& t, void* dev_buf, hip
   const int n = (int)act.size();
   std::vector<MultiItem<OpCocgPX<T>>> st[2];
   std::vector<FinishItem<OpFinish<OpCocgPX<T>>>> f1[2];
-  std::vector<PcocgItem<T>> up[2];
+  std::vector<OtfItem<T>> up[2];
   std::vector<FinishItem<CocgFinish>> f2;
   int sb = 0, ub = 0;
   for (int i = 0; i < n; ++i) {
@@ -192,7 +192,7 @@ fit_status build_tables(std::vector<Sys*>& act, Tables<T>& t, void* dev_buf, hip
     ts.zc = zc_for(y.g, dtype, t.shape);
     const StencilLaunch L = make_launch(y.g->view, ts, y.omega);
     const int nb = launch_blocks(L);
-    const int nu = pw_blocks(y.g->ne);
+    const int nu = otf_shape(y.g->view, y.max_blocks).blocks;
     if (nb > y.max_blocks || nu > y.max_blocks) {
       set_error("fit_sweep: internal launch larger than its partials buffer");
       return FIT_E_DEVICE;
@@ -204,8 +204,7 @@ fit_status build_tables(std::vector<Sys*>& act, Tables<T>& t, void* dev_buf, hip
                      (T)(y.omega * y.omega), {}, {}};
       st[par].push_back(MultiItem<OpCocgPX<T>>{y.g->view, L, op, sb, nb});
       f1[par].push_back(FinishItem<OpFinish<OpCocgPX<T>>>{y.part, nb, OpFinish<OpCocgPX<T>>{op}});
-      up[par].push_back(PcocgItem<T>{y.g->ne, (T*)y.d, (T*)y.ri, (T*)y.z, p_new, (const T*)y.q,
-                                     (const T*)y.m, y.st, y.part, ub, nu});
+      up[par].push_back(OtfItem<T>{y.g->view, y.omega, (T*)y.ri, (const T*)y.q, y.st, y.part, ub, nu});
     }
     f2.push_back(FinishItem<CocgFinish>{y.part, nu, CocgFinish{y.st}});
     sb += nb;
@@ -238,7 +237,7 @@ template <class T>
 size_t table_bytes(int n) {
   return 2 * (align_up(sizeof(MultiItem<OpCocgPX<T>>) * n, 256) +
               align_up(sizeof(FinishItem<OpFinish<OpCocgPX<T>>>) * n, 256) +
-              align_up(sizeof(PcocgItem<T>) * n, 256)) +
+              align_up(sizeof(OtfItem<T>) * n, 256)) +
          align_up(sizeof(FinishItem<CocgFinish>) * n, 256) + 4096;
 }
 
@@ -252,8 +251,8 @@ fit_status one_iter(const Tables<T>& t, int par, hipStream_t s) {
                      t.fin1[par]);
   FIT_HIP(hipGetLastError());
   const int tok = prof_begin(s);
-  hipLaunchKernelGGL(pcocg_rupdate_multi_kernel<T>, dim3(t.upd_blocks), dim3(256), 0, s, t.upd[par],
-                     t.n);
+  hipLaunchKernelGGL((pcocg_rupdate_otf_multi_kernel<T, kOtfZc>), dim3(t.upd_blocks), dim3(256), 0, s,
+                     t.upd[par], t.n);
   FIT_HIP(hipGetLastError());
   prof_end(tok, s, sizeof(T) == 8 ? "sweep_cocg_update_c128" : "sweep_cocg_update_c64");
   hipLaunchKernelGGL((finish_multi_kernel<3, CocgFinish>), dim3(t.n), dim3(256), 0, s, t.fin2);
