@@ -592,7 +592,7 @@ __global__ void __launch_bounds__(256)
 struct OtfShape {
   int zc, blocks;
 };
-constexpr int kOtfZc = 4;
+constexpr int kOtfZc = 2;
 inline OtfShape otf_shape(const GridView& g, int max_blocks) {
   const int zc = kOtfZc;
   const int64_t nbxy = ((int64_t)g.nx * g.ny + 255) / 256, nbz = (g.nz + zc - 1) / zc;
