@@ -352,7 +352,11 @@ fit_status fit_precond_create(const fit_precond_cfg *cfg, int device, struct fit
 fit_status fit_precond_save(const struct fit_precond *p, void *blob, size_t *n);
 fit_status fit_precond_load(const void *blob, size_t n, int device, struct fit_precond **out);
 /* z = M(v) for one complex128 edge vector on grid g at omega (the unscaled
- * form).  v_dev, z_dev: n_e complex128 on the grid's device.  Synchronous. */
+ * form).  v_dev, z_dev: n_e complex128 on the grid's device.  Synchronous.
+ * The first preconditioner call on a grid computes its edge mask (n_e bytes)
+ * and keeps it with the grid until fit_grid_destroy; the activations of the
+ * last padded grid size are kept with the preconditioner (reallocated when
+ * the size changes). */
 fit_status fit_precond_apply(struct fit_precond *p, const struct fit_grid *g, double omega,
                              const void *v_dev, void *z_dev, void *stream);
 /* Training objective of one pair over the whole grid (padded to multiples of

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -348,6 +349,10 @@ struct fit_grid {
   fit::Workspace ws;
   fit::Workspace red;  // reduction partials + counters + solver state
   void* pinned = nullptr;  // pinned host mirror of the solver state
+  // edge mask (1 = free edge), computed on first use by the learned
+  // preconditioner and kept until destroy
+  uint8_t* d_mask = nullptr;
+  std::mutex mask_mu;
 };
 
 namespace fit {

@@ -329,6 +329,7 @@ extern "C" void fit_grid_destroy(fit_grid* g) {
   if (g->ws.ptr) (void)hipFree(g->ws.ptr);
   if (g->red.ptr) (void)hipFree(g->red.ptr);
   if (g->pinned) (void)hipHostFree(g->pinned);
+  if (g->d_mask) (void)hipFree(g->d_mask);
   delete g->host_ports;
   delete g->host_mats;
   delete g;

@@ -881,15 +881,26 @@ fit_status backward(fit_precond* p, Acts& a, float scale, hipStream_t s) {
   return FIT_OK;
 }
 
+// The grid's edge mask, computed on the first request and cached in the grid
+// (which owns it); ready for use on any stream when this returns.
 fit_status edge_mask_of(const fit_grid* g, uint8_t** out, hipStream_t s) {
-  void* m = nullptr;
-  FIT_HIP(hipMalloc(&m, (size_t)g->ne));
-  fit_status st = fit_edge_mask(g, (uint8_t*)m, s);
-  if (st != FIT_OK) {
-    (void)hipFree(m);
-    return st;
+  fit_grid* gm = const_cast<fit_grid*>(g);  // the cache is not part of the grid's value
+  std::lock_guard<std::mutex> lk(gm->mask_mu);
+  if (!gm->d_mask) {
+    void* m = nullptr;
+    FIT_HIP(hipMalloc(&m, (size_t)g->ne));
+    fit_status st = fit_edge_mask(g, (uint8_t*)m, s);
+    if (st == FIT_OK) {
+      const hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) st = hip_fail(e, "edge mask");
+    }
+    if (st != FIT_OK) {
+      (void)hipFree(m);
+      return st;
+    }
+    gm->d_mask = (uint8_t*)m;
   }
-  *out = (uint8_t*)m;
+  *out = gm->d_mask;
   return FIT_OK;
 }
 
@@ -1071,7 +1082,6 @@ struct UNetApply : PrecondApply {
   uint8_t* mask = nullptr;
   void* tmp[2] = {nullptr, nullptr};
   ~UNetApply() override {
-    (void)hipFree(mask);
     (void)hipFree(tmp[0]);
     (void)hipFree(tmp[1]);
   }
@@ -1202,7 +1212,6 @@ extern "C" fit_status fit_precond_apply(fit_precond* p, const fit_grid* g, doubl
   if (st != FIT_OK) return st;
   st = apply_grid<double>(p, g, omega, (const double*)v_dev, (double*)z_dev, mask, s);
   hipError_t e = hipStreamSynchronize(s);
-  (void)hipFree(mask);
   if (st == FIT_OK && e != hipSuccess) st = hip_fail(e, "fit_precond_apply");
   return st;
 }
@@ -1235,7 +1244,6 @@ extern "C" fit_status fit_precond_loss_grad(fit_precond* p, const fit_grid* g, d
   if (st == FIT_OK && grad_host &&
       hipMemcpy(grad_host, p->G, sizeof(float) * (size_t)p->nparams, hipMemcpyDeviceToHost) != hipSuccess)
     st = FIT_E_DEVICE;
-  (void)hipFree(mask);
   return st;
 }
 
@@ -1296,7 +1304,6 @@ extern "C" fit_status fit_precond_train(fit_grid* const* train, int ntrain, cons
   for (int i = 0; i < ntrain; ++i) ne_max = std::max(ne_max, train[i]->ne);
   double *e = nullptr, *e2 = nullptr, *r = nullptr, *hist = nullptr;
   auto cleanup = [&]() {
-    for (uint8_t* m : masks) (void)hipFree(m);
     (void)hipFree(e);
     (void)hipFree(e2);
     (void)hipFree(r);
