@@ -268,16 +268,17 @@ __global__ void __launch_bounds__(256)
   const int64_t nb = (int64_t)ex * ey * ez;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nb;
        q += (int64_t)gridDim.x * blockDim.x) {
-    const int bx = (int)(q % ex), by = (int)((q / ex) % ey), bz = (int)(q / ((int64_t)ex * ey));
-    const int i = ox0 + bx, j = oy0 + by, k = oz0 + bz;
+    const uint32_t qq = (uint32_t)q, t = qq / (uint32_t)ex, bx = qq - t * (uint32_t)ex;
+    const uint32_t bz = t / (uint32_t)ey, by = t - bz * (uint32_t)ey;
+    const int i = ox0 + (int)bx, j = oy0 + (int)by, k = oz0 + (int)bz;
     if (i >= g.nx || j >= g.ny || k >= g.nz) continue;
     const int64_t n = ((int64_t)k * g.ny + j) * g.nx + i;
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
-      if (!mask[3 * n + w]) continue;
       const cx<T> a = ldc(v, 3 * n + w);
-      acc[0] += cabs2_d(a);
-      acc[1] += 1.0;
+      const bool fr = mask[3 * n + w] != 0;
+      acc[0] += fr ? cabs2_d(a) : 0.0;
+      acc[1] += fr ? 1.0 : 0.0;
     }
   }
   block_partial<2>(acc, part, lds);
@@ -327,8 +328,9 @@ __global__ void features_kernel(GridView g, const T* v, const uint8_t* mask, con
   const float lw = (float)(log10(omega / (2.0 * kPi) / 1e9) / 1.6);
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
        q += (int64_t)gridDim.x * blockDim.x) {
-    const int bx = (int)(q % X), by = (int)((q / X) % Y), bz = (int)(q / ((int64_t)X * Y));
-    const int i = ox0 + bx, j = oy0 + by, k = oz0 + bz;
+    const uint32_t qq = (uint32_t)q, t = qq / (uint32_t)X, bx = qq - t * (uint32_t)X;
+    const uint32_t bz = t / (uint32_t)Y, by = t - bz * (uint32_t)Y;
+    const int i = ox0 + (int)bx, j = oy0 + (int)by, k = oz0 + (int)bz;
     float f[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) f[c] = 0.f;
@@ -336,11 +338,10 @@ __global__ void features_kernel(GridView g, const T* v, const uint8_t* mask, con
       const int64_t n = ((int64_t)k * g.ny + j) * g.nx + i;
 #pragma unroll
       for (int w = 0; w < 3; ++w) {
-        if (mask[3 * n + w]) {
-          const cx<T> a = ldc(v, 3 * n + w);
-          f[2 * w] = (float)((double)a.re * inv);
-          f[2 * w + 1] = (float)((double)a.im * inv);
-        }
+        const cx<T> a = ldc(v, 3 * n + w);
+        const bool fr = mask[3 * n + w] != 0;
+        f[2 * w] = fr ? (float)((double)a.re * inv) : 0.f;
+        f[2 * w + 1] = fr ? (float)((double)a.im * inv) : 0.f;
       }
       const int a = min(i, g.ncx - 1), b = min(j, g.ncy - 1), c = min(k, g.ncz - 1);
       const MatEntry& me = g.mats[g.cell[g.cell_index(a, b, c)]];
@@ -368,16 +369,22 @@ template <class T>
 __global__ void output_kernel(GridView g, const float* y, const uint8_t* mask, const double* scal, int slot,
                               int X, int Y, T* z) {
   const double s = scal[slot];
+  const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.np;
        n += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(n % g.nx), j = (int)((n / g.nx) % g.ny), k = (int)(n / ((int64_t)g.nx * g.ny));
+    // 32-bit index arithmetic (a grid has fewer than 2^31 nodes); every load
+    // is issued before any is used
+    const uint32_t nn = (uint32_t)n, t = nn / nx, i = nn - t * nx, k = t / ny, j = t - k * ny;
     const int64_t vx = ((int64_t)k * Y + j) * X + i;
-#pragma unroll
-    for (int w = 0; w < 3; ++w) {
-      cx<T> o{T(0), T(0)};
-      if (mask[3 * n + w]) o = cx<T>{(T)(s * y[vx * 8 + 2 * w]), (T)(s * y[vx * 8 + 2 * w + 1])};
-      stc(z, 3 * n + w, o);
-    }
+    const float4 y03 = *reinterpret_cast<const float4*>(y + vx * 8);
+    const float2 y45 = *reinterpret_cast<const float2*>(y + vx * 8 + 4);
+    const uint8_t m0 = mask[3 * n], m1 = mask[3 * n + 1], m2 = mask[3 * n + 2];
+    const cx<T> o0{(T)(s * y03.x), (T)(s * y03.y)}, o1{(T)(s * y03.z), (T)(s * y03.w)},
+        o2{(T)(s * y45.x), (T)(s * y45.y)};
+    const cx<T> zero{T(0), T(0)};
+    stc(z, 3 * n, m0 ? o0 : zero);
+    stc(z, 3 * n + 1, m1 ? o1 : zero);
+    stc(z, 3 * n + 2, m2 ? o2 : zero);
   }
 }
 
@@ -396,8 +403,9 @@ __global__ void __launch_bounds__(256)
   const double nf = counts[1] > 0.0 ? counts[1] : 1.0;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv;
        q += (int64_t)gridDim.x * blockDim.x) {
-    const int bx = (int)(q % X), by = (int)((q / X) % Y), bz = (int)(q / ((int64_t)X * Y));
-    const int i = ox0 + bx, j = oy0 + by, k = oz0 + bz;
+    const uint32_t qq = (uint32_t)q, t = qq / (uint32_t)X, bx = qq - t * (uint32_t)X;
+    const uint32_t bz = t / (uint32_t)Y, by = t - bz * (uint32_t)Y;
+    const int i = ox0 + (int)bx, j = oy0 + (int)by, k = oz0 + (int)bz;
     float d[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (i < g.nx && j < g.ny && k < g.nz) {
       const int64_t n = ((int64_t)k * g.ny + j) * g.nx + i;
@@ -441,7 +449,8 @@ __global__ void noise_kernel(int64_t ne, const uint8_t* mask, uint64_t seed, dou
 __global__ void smooth_kernel(GridView g, const uint8_t* mask, const double* in, double* out) {
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.np;
        n += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(n % g.nx), j = (int)((n / g.nx) % g.ny), k = (int)(n / ((int64_t)g.nx * g.ny));
+    const uint32_t nn = (uint32_t)n, t = nn / (uint32_t)g.nx, k32 = t / (uint32_t)g.ny;
+    const int i = (int)(nn - t * (uint32_t)g.nx), j = (int)(t - k32 * (uint32_t)g.ny), k = (int)k32;
     const int64_t sx = 1, sy = g.nx, sz = (int64_t)g.nx * g.ny;
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
