@@ -42,12 +42,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tile):
+def measured_traffic(tile, path=None):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source
     and with the tile this run uses."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path or TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -120,7 +120,7 @@ def _counter_run_info(log_path):
     raise SystemExit(f"{log_path}: no line from a --counters run")
 
 
-def ingest_counters(fetch_csv, write_csv, fetch_log, write_log, commands):
+def ingest_counters(fetch_csv, write_csv, fetch_log, write_log, commands, out_path=None):
     """Turn the two rocprofv3 counter CSVs of `--counters` into the per-launch
     HBM traffic of the fused COCG step-1 kernel, each counter scaled by what
     it reads for the copy-shaped calibration kernel.  Both runs must have
@@ -162,7 +162,7 @@ def ingest_counters(fetch_csv, write_csv, fetch_log, write_log, commands):
         out[f"{key}_scale"] = scale
         out[f"{key}_bytes_per_launch"] = kib * 1024.0 * scale
     out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(out_path or TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
 
