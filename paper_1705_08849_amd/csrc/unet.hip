@@ -625,10 +625,14 @@ fit_status gemm(const GemmArgs& g, int64_t n_cols, hipStream_t s, int splits = 1
   if (a.gather == G_CONV3 && splits == 1 && lds_cin && a.K == 27LL * a.cin && a.ox == a.ix && a.oy == a.iy &&
       a.M == (int64_t)a.ix * a.iy * a.iz && !a.up) {
     const int64_t nb = (int64_t)((a.ix + kBrX - 1) / kBrX) * ((a.iy + kBrY - 1) / kBrY) * ((a.iz + kBrZ - 1) / kBrZ);
-    const dim3 grid((unsigned)nb, (unsigned)((n_cols + nt - 1) / nt), 1);
+    // small coarse levels: narrower column tiles give more workgroups (the B
+    // rows stay padded to the wider tile, a multiple of the narrower one)
+    int ntc = nt;
+    while (ntc > 16 && nb * ((n_cols + ntc - 1) / ntc) < 1024) ntc /= 2;
+    const dim3 grid((unsigned)nb, (unsigned)((n_cols + ntc - 1) / ntc), 1);
     const int tok = prof_begin(s);
 #define CONV(NT, CI) \
-  if (nt == NT && a.cin == CI) hipLaunchKernelGGL((conv3_lds_kernel<NT, CI>), grid, dim3(256), 0, s, a);
+  if (ntc == NT && a.cin == CI) hipLaunchKernelGGL((conv3_lds_kernel<NT, CI>), grid, dim3(256), 0, s, a);
     CONV(16, 8) CONV(16, 16) CONV(16, 32) CONV(16, 64) CONV(32, 8) CONV(32, 16) CONV(32, 32) CONV(32, 64)
     CONV(64, 8) CONV(64, 16) CONV(64, 32) CONV(64, 64)
 #undef CONV
