@@ -256,13 +256,14 @@ __global__ void __launch_bounds__(256) igemm_kernel(GemmArgs p) {
 // LDS layout: voxel h of the halo brick holds C8 = CIN/8 16-byte chunks;
 // chunk c is stored at slot c ^ ((h / (8 / C8)) & (C8 - 1)), so the eight
 // lanes of an octet (same chunk, eight consecutive voxels) read eight
-// different 16-byte slots.  On gfx950 a 16-byte read is served 16 lanes at a
-// time and runs conflict-free only when each octet stays inside one 128-byte
-// half of a 256-byte window and the two octets use different halves; the two
-// x-rows of a subtile do not satisfy that, which costs four extra LDS cycles
-// per read (measured with SQ_LDS_BANK_CONFLICT).  A layout that avoids it
-// (slot position = x mod 8 + 8 (y mod 2)) pads the halo to about 1.6x the
-// LDS and so fits fewer workgroups per CU; it is not used.
+// different 16-byte slots.  Measured on gfx950 (SQ_LDS_BANK_CONFLICT, 16-byte
+// reads): 16 lanes that read one aligned 256-byte block, in any order, take
+// no extra cycle; 16 lanes spread over two blocks take extra cycles even when
+// their banks differ.  A subtile's rows are two x-rows of 8 voxels and each
+// tap shifts them by dx, so no single-copy layout keeps every tap inside one
+// block; this one costs four extra LDS cycles per read.  (A chunk-planar
+// layout padded to 16-voxel x-groups, conflict-free for dx = 0 only, was
+// measured slower: more LDS per workgroup, more conflicts in total.)
 // LDS: 600 * CIN * 2 bytes (9.6 / 19.2 / 38.4 / 76.8 KB).
 constexpr int kBrX = 8, kBrY = 8, kBrZ = 4;
 constexpr int kHaX = kBrX + 2, kHaY = kBrY + 2, kHaZ = kBrZ + 2;
