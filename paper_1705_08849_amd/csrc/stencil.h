@@ -193,8 +193,10 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
   op.begin();
 
   __shared__ MatLds<T> mat;
-  __shared__ cx<T> X[3][BY][BX];
-  __shared__ cx<T> H[3][BY - 1][BX - 1];
+  // staged planes and facets, double-buffered by plane parity so that one
+  // barrier per plane separates every write from its readers
+  __shared__ cx<T> X[2][3][BY][BX];
+  __shared__ cx<T> H[2][3][BY - 1][BX - 1];
   __shared__ double red_lds[NR * (NT / 64)];
 
   const int tid = threadIdx.x;
@@ -288,10 +290,15 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
       }
     }
   };
-  auto advance = [&]() {
+  // the staged plane becomes the current one: its values into LDS buffer b,
+  // its coefficients into registers
+  auto stage_lds = [&](int b) {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) X[b][w][ty][tx] = sn.xs[w];
+  };
+  auto advance_regs = [&]() {
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
-      X[w][ty][tx] = sn.xs[w];
       cur_cf[w] = sn.cf[w];
       cur_nu[w] = sn.nu[w];
       if (SYM) cur_xr[w] = sn.xr[w];
@@ -302,7 +309,8 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
   // ---- prologue: stage planes ks and ks+1, prefetch ks+2 -----------------
   fetch(ks, pa);
   process(ks, pa);
-  advance();
+  stage_lds(0);
+  advance_regs();
   fetch(ks + 1, pb);
   process(ks + 1, pb);
   fetch(ks + 2, pa);
@@ -313,32 +321,37 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
   for (int q = 0; q < NR; ++q) acc[q] = 0.0;
   cx<T> hpx = {T(0), T(0)}, hpy = {T(0), T(0)};  // own facets of the plane below
 
-  // One plane step: facets of plane k, gather onto its edges, then stage
-  // plane k+2 from `use` and prefetch plane k+3 into `next`.
-  auto step = [&](int k, Pending& use, Pending& next) {
+  // One plane step (plane k in LDS buffer b): facets of plane k, plane k+1
+  // into buffer b^1, one barrier, gather onto plane k's edges, then stage
+  // plane k+2 from `use` and prefetch plane k+3 into `next`.  Buffer b's
+  // facets are rewritten two steps later, after the next barrier, which
+  // every reader of them has passed; buffer b^1's values were last read
+  // before the previous barrier.
+  auto step = [&](int k, int b, Pending& use, Pending& next) {
     // ---- C: facets of plane k (tile + low halo ring) ----------------------
     cx<T> xo[3];
     cx<T> hx = {T(0), T(0)}, hy = {T(0), T(0)}, hz = {T(0), T(0)};
 #pragma unroll
-    for (int w = 0; w < 3; ++w) xo[w] = X[w][ty][tx];
+    for (int w = 0; w < 3; ++w) xo[w] = X[b][w][ty][tx];
     if (facets) {
-      const cx<T> xz_jp = X[2][ty + 1][tx], xx_jp = X[0][ty + 1][tx];
-      const cx<T> xz_ip = X[2][ty][tx + 1], xy_ip = X[1][ty][tx + 1];
+      const cx<T> xz_jp = X[b][2][ty + 1][tx], xx_jp = X[b][0][ty + 1][tx];
+      const cx<T> xz_ip = X[b][2][ty][tx + 1], xy_ip = X[b][1][ty][tx + 1];
       hx = cur_nu[0] * (xz_jp - xo[2] - sn.xs[1] + xo[1]);
       hy = cur_nu[1] * (sn.xs[0] - xo[0] - xz_ip + xo[2]);
       hz = cur_nu[2] * (xy_ip - xo[1] - xx_jp + xo[0]);
-      H[0][ty][tx] = hx;
-      H[1][ty][tx] = hy;
-      H[2][ty][tx] = hz;
+      H[b][0][ty][tx] = hx;
+      H[b][1][ty][tx] = hy;
+      H[b][2][ty][tx] = hz;
     }
+    stage_lds(b ^ 1);
     __syncthreads();
 
     // ---- E: gather C^T h onto the owned node's edges ----------------------
     if (owner && k >= kb) {
       cx<T> y[3];
-      y[0] = hpy - hy + hz - H[2][ty - 1][tx];
-      y[1] = H[2][ty][tx - 1] - hz + hx - hpx;
-      y[2] = H[0][ty - 1][tx] - hx + hy - H[1][ty][tx - 1];
+      y[0] = hpy - hy + hz - H[b][2][ty - 1][tx];
+      y[1] = H[b][2][ty][tx - 1] - hz + hx - hpx;
+      y[2] = H[b][0][ty - 1][tx] - hx + hy - H[b][1][ty][tx - 1];
       const cx<T>* xr = SYM ? cur_xr : xo;
 #pragma unroll
       for (int w = 0; w < 3; ++w) {
@@ -356,19 +369,18 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
     hpx = hx;
     hpy = hy;
 
-    // ---- advance: plane k+1 into LDS, stage k+2, prefetch k+3 -------------
-    advance();
+    // ---- advance: plane k+1 becomes current, stage k+2, prefetch k+3 ------
+    advance_regs();
     process(k + 2, use);
     fetch(k + 3, next);
-    __syncthreads();
   };
 
   int k = ks;
   for (; k + 1 < ke; k += 2) {
-    step(k, pa, pb);
-    step(k + 1, pb, pa);
+    step(k, 0, pa, pb);
+    step(k + 1, 1, pb, pa);
   }
-  if (k < ke) step(k, pa, pb);
+  if (k < ke) step(k, 0, pa, pb);
 
   if (Op::NRED > 0) block_partial_at<NR>(acc, op.partials(), red_lds, lb);
 }
