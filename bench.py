@@ -369,17 +369,26 @@ def main():
     # plain operator bandwidth (the metric's second part)
     xv = torch.randn(dev.n_edges, dtype=torch.complex128, device="cuda:0")
     yv = torch.empty_like(xv)
-    for _ in range(3):
-        g.matvec(omega, xv, yv, scaling="none")
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(20):
-        g.matvec(omega, xv, yv, scaling="none")
-    e1.record()
-    torch.cuda.synchronize()
-    mv_us = e0.elapsed_time(e1) * 1000 / 20
+    def mean_us(fn, reps=20):
+        """Mean launch time over `reps` back-to-back launches between two HIP
+        events (events around each launch would add the event overhead)."""
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1000 / reps
+
+    mv_us = mean_us(lambda: g.matvec(omega, xv, yv, scaling="none"))
     mv_bytes = n_nodes * 6 * 16 + n_cells
+    # the box's device copy bandwidth on vectors of the same size, as a
+    # second reference besides the 8 TB/s peak
+    cp_us = mean_us(lambda: yv.copy_(xv))
+    copy_gbs = 2 * xv.numel() * 16 / cp_us / 1e3
     del xv, yv
 
     def step():
@@ -420,7 +429,7 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(tile), "kernel": kname,
                 "avg_launch_us": round(avg_s * 1e6, 2), "alg_bytes_per_launch": alg,
-                "launches": launches}
+                "launches": launches, "frac_of_copy": round(achieved / copy_gbs, 4)}
     share = {k: round(v[1] / 1e3 / elapsed, 3) for k, v in sorted(stats.items())}
     iters = int(np.mean([i["iterations"] for i, _ in infos])) if infos else 0
     out = {
@@ -449,11 +458,14 @@ def main():
             "iterations_per_point": iters,
             "true_relres": [i["true_relres"] for i, _ in infos],
             "grid_create_s": round(t_create, 4),
+            "value_incl_grid_create": round(len(ok) / (elapsed + t_create), 6),
         },
         "matvec": {"kernel": "matvec A(omega) c128", "us": round(mv_us, 2),
                    "achieved": round(mv_bytes / mv_us / 1e3, 1), "unit": "GB/s",
                    "frac": round(mv_bytes / mv_us / 1e3 / HBM_PEAK_GBS, 4),
-                   "alg_bytes": mv_bytes},
+                   "alg_bytes": mv_bytes, "timing": "mean of 20 back-to-back launches, HIP events",
+                   "copy_gbs": round(copy_gbs, 1),
+                   "frac_of_copy": round(mv_bytes / mv_us / 1e3 / copy_gbs, 4)},
         "roofline": roof,
         "kernel_time_share": share,
     }
