@@ -324,6 +324,8 @@ def main():
                     help="with --autotune: write the tile table to the committed file")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the secondary rows (batched sweep, learned preconditioner)")
+    ap.add_argument("--row", choices=["sweep", "precond"],
+                    help="run only this secondary row and print it as one JSON line")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short sample profiled by the HBM-counter passes")
     ap.add_argument("--ingest", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_LOG", "WRITE_LOG"),
@@ -342,6 +344,17 @@ def main():
         sys.exit(2)
     if args.counters:
         counter_sample(args)
+        return
+    if args.row:
+        import numpy as np
+        import torch
+
+        from paper_1705_08849_amd import devices as D
+        from paper_1705_08849_amd import fit
+
+        torch.cuda.init()
+        fn = {"sweep": sweep_row, "precond": precond_row}[args.row]
+        print(json.dumps({"row": args.row, **fn(fit, D, np, torch, not args.no_cpu_baseline)}), flush=True)
         return
 
     import numpy as np

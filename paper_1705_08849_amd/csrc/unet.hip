@@ -146,33 +146,46 @@ __global__ void relu_bwd_kernel(const float* g, int64_t g_ld, const bf16* out, i
 // zero in the padding columns v in [nv, ld).
 __global__ void im2colT_kernel(const bf16* a, int64_t a_ld, int cip, int kind, int ix, int iy, int iz,
                                int ox, int oy, int64_t nv, int64_t kf, bf16* xt, int64_t ld) {
-  const int64_t total = kf * ld;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t v = q % ld, k = q / ld;
+  // blockIdx.y: row k (tap, channel), uniform over the block; threads over
+  // the voxels v of that row, 32-bit index arithmetic (nv < 2^31)
+  const int k = (int)blockIdx.y;
+  const int tap = k / cip, ci = k - tap * cip;
+  int dx, dy, dz;
+  if (kind == L_CONV3) {
+    dx = tap % 3 - 1;
+    dy = (tap / 3) % 3 - 1;
+    dz = tap / 9 - 1;
+  } else {
+    dx = tap & 1;
+    dy = (tap >> 1) & 1;
+    dz = tap >> 2;
+  }
+  const uint32_t uox = (uint32_t)ox, uoy = (uint32_t)oy;
+  bf16* out = xt + (int64_t)k * ld;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < ld; v += (int64_t)gridDim.x * blockDim.x) {
     bf16 val = (bf16)0.f;
     if (v < nv) {
-      const int tap = (int)(k / cip), ci = (int)(k % cip);
       if (kind == L_PW) {
         val = a[v * a_ld + ci];
       } else {
-        const int mx = (int)(v % ox), my = (int)((v / ox) % oy), mz = (int)(v / ((int64_t)ox * oy));
+        const uint32_t uv = (uint32_t)v, t = uv / uox, mx = uv - t * uox, mz = t / uoy, my = t - mz * uoy;
         int x, y, z;
         if (kind == L_CONV3) {
-          x = mx + tap % 3 - 1;
-          y = my + (tap / 3) % 3 - 1;
-          z = mz + tap / 9 - 1;
+          x = (int)mx + dx;
+          y = (int)my + dy;
+          z = (int)mz + dz;
         } else {
-          x = 2 * mx + (tap & 1);
-          y = 2 * my + ((tap >> 1) & 1);
-          z = 2 * mz + (tap >> 2);
+          x = 2 * (int)mx + dx;
+          y = 2 * (int)my + dy;
+          z = 2 * (int)mz + dz;
         }
         if (x >= 0 && y >= 0 && z >= 0 && x < ix && y < iy && z < iz)
           val = a[(((int64_t)z * iy + y) * ix + x) * a_ld + ci];
       }
     }
-    xt[q] = val;
+    out[v] = val;
   }
+  (void)kf;
 }
 
 // dT[n][v] = dpre[v][n] for n < cop (rows up to nrows zero), zero padding v >= nv.
@@ -223,15 +236,23 @@ __global__ void reduce_dw_kernel(const float* part, int splits, int64_t M, int64
   }
 }
 
-__global__ void __launch_bounds__(256) bias_grad_kernel(const bf16* dt, int64_t ld, int cout, int up,
-                                                        float scale, float* gb) {
-  __shared__ double lds[4];
+__global__ void __launch_bounds__(1024) bias_grad_kernel(const bf16* dt, int64_t ld, int cout, int up,
+                                                         float scale, float* gb) {
+  // one block per output channel; 16-byte loads (rows are padded to a
+  // multiple of 32 elements, so ld / 8 vectors cover a row exactly)
+  __shared__ double lds[1024 / 64];
   const int c = blockIdx.x;
   double acc[1] = {0.0};
   const int reps = up ? 8 : 1;
   for (int t = 0; t < reps; ++t) {
-    const bf16* row = dt + ((int64_t)t * cout + c) * ld;
-    for (int64_t v = threadIdx.x; v < ld; v += blockDim.x) acc[0] += (double)(float)row[v];
+    const bf16x8* row = reinterpret_cast<const bf16x8*>(dt + ((int64_t)t * cout + c) * ld);
+    for (int64_t v = threadIdx.x; v < ld / 8; v += blockDim.x) {
+      const bf16x8 x = row[v];
+      float f = 0.f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) f += (float)x[e];
+      acc[0] += (double)f;
+    }
   }
   block_reduce<1>(acc, lds);
   if (threadIdx.x == 0) gb[c] += scale * (float)acc[0];
@@ -767,8 +788,9 @@ fit_status layer_bwd(fit_precond* p, Acts& a, const DevLayer& L, const bf16* in,
     return FIT_E_DEVICE;
   }
   const int gk = up ? L_PW : sp.kind;
-  hipLaunchKernelGGL(im2colT_kernel, dim3(nblk(M * ld)), dim3(256), 0, s, in, in_ld, cip, gk, bi.X, bi.Y,
-                     bi.Z, up ? bi.X : bo.X, up ? bi.Y : bo.Y, nv_w, M, a.xt, ld);
+  hipLaunchKernelGGL(im2colT_kernel, dim3((unsigned)std::min<int64_t>(64, (ld + 255) / 256), (unsigned)M),
+                     dim3(256), 0, s, in, in_ld, cip, gk, bi.X, bi.Y, bi.Z, up ? bi.X : bo.X,
+                     up ? bi.Y : bo.Y, nv_w, M, a.xt, ld);
   FIT_HIP(hipGetLastError());
   hipLaunchKernelGGL(dgradT_kernel, dim3(nblk((int64_t)std::max(nrows, cop) * ld)), dim3(256), 0, s, dpre,
                      cop, sp.cout, up ? 1 : 0, bi.X, bi.Y, nv_w, std::max(nrows, cop), a.dt, ld);
@@ -795,7 +817,7 @@ fit_status layer_bwd(fit_precond* p, Acts& a, const DevLayer& L, const bf16* in,
   hipLaunchKernelGGL(reduce_dw_kernel, dim3(nblk(nw)), dim3(256), 0, s, a.part, splits, M, ncols, sp.kind,
                      sp.taps, sp.cin, sp.cout, scale, p->G + L.w_off);
   FIT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(bias_grad_kernel, dim3(sp.cout), dim3(256), 0, s, a.dt, ld, sp.cout, up ? 1 : 0, scale,
+  hipLaunchKernelGGL(bias_grad_kernel, dim3(sp.cout), dim3(1024), 0, s, a.dt, ld, sp.cout, up ? 1 : 0, scale,
                      p->G + L.b_off);
   FIT_HIP(hipGetLastError());
   // 3. input gradient
