@@ -142,50 +142,74 @@ __global__ void relu_bwd_kernel(const float* g, int64_t g_ld, const bf16* out, i
   }
 }
 
-// XT[k][v] = A_fwd(v, k) of a conv3 / down2 / pointwise gather (k = tap*cip + ci),
-// zero in the padding columns v in [nv, ld).
-__global__ void im2colT_kernel(const bf16* a, int64_t a_ld, int cip, int kind, int ix, int iy, int iz,
-                               int ox, int oy, int64_t nv, int64_t kf, bf16* xt, int64_t ld) {
-  // blockIdx.y: row k (tap, channel), uniform over the block; threads over
-  // the voxels v of that row, 32-bit index arithmetic (nv < 2^31)
-  const int k = (int)blockIdx.y;
-  const int tap = k / cip, ci = k - tap * cip;
-  int dx, dy, dz;
+// xt[k][v] = the layer input at voxel v + offset(tap(k)), channel ci(k)
+// (k = tap * cip + ci), zero outside the tensor and for v >= nv: the
+// transposed im2col of the weight-gradient GEMM.  A workgroup owns one tap
+// and 256 voxels: it reads their channels (up to 64 at a time) with 16-byte
+// loads from the channels-last input, transposes them through LDS, and
+// writes its tap's rows with 16-byte stores (8 consecutive voxels per lane).
+constexpr int kIm2colMaxC = 64;
+__global__ void __launch_bounds__(256)
+    im2colT_kernel(const bf16* a, int64_t a_ld, int cip, int kind, int ix, int iy, int iz, int ox, int oy,
+                   int64_t nv, bf16* xt, int64_t ld) {
+  __shared__ bf16 tr[kIm2colMaxC][256 + 8];  // +8: rows start on different banks
+  const int tap = (int)blockIdx.y;
+  const int64_t v0 = (int64_t)blockIdx.x * 256;
+  int dx = 0, dy = 0, dz = 0;
   if (kind == L_CONV3) {
     dx = tap % 3 - 1;
     dy = (tap / 3) % 3 - 1;
     dz = tap / 9 - 1;
-  } else {
+  } else if (kind == L_DOWN2) {
     dx = tap & 1;
     dy = (tap >> 1) & 1;
     dz = tap >> 2;
   }
-  const uint32_t uox = (uint32_t)ox, uoy = (uint32_t)oy;
-  bf16* out = xt + (int64_t)k * ld;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < ld; v += (int64_t)gridDim.x * blockDim.x) {
-    bf16 val = (bf16)0.f;
+  // 1. this thread's voxel: gather its cip channels
+  {
+    const int64_t v = v0 + threadIdx.x;
+    int64_t src = -1;
     if (v < nv) {
       if (kind == L_PW) {
-        val = a[v * a_ld + ci];
+        src = v;
       } else {
-        const uint32_t uv = (uint32_t)v, t = uv / uox, mx = uv - t * uox, mz = t / uoy, my = t - mz * uoy;
-        int x, y, z;
-        if (kind == L_CONV3) {
-          x = (int)mx + dx;
-          y = (int)my + dy;
-          z = (int)mz + dz;
-        } else {
-          x = 2 * (int)mx + dx;
-          y = 2 * (int)my + dy;
-          z = 2 * (int)mz + dz;
-        }
-        if (x >= 0 && y >= 0 && z >= 0 && x < ix && y < iy && z < iz)
-          val = a[(((int64_t)z * iy + y) * ix + x) * a_ld + ci];
+        const uint32_t uv = (uint32_t)v, t = uv / (uint32_t)ox, mx = uv - t * (uint32_t)ox;
+        const uint32_t mz = t / (uint32_t)oy, my = t - mz * (uint32_t)oy;
+        const int x = (kind == L_CONV3 ? (int)mx : 2 * (int)mx) + dx;
+        const int y = (kind == L_CONV3 ? (int)my : 2 * (int)my) + dy;
+        const int z = (kind == L_CONV3 ? (int)mz : 2 * (int)mz) + dz;
+        if (x >= 0 && y >= 0 && z >= 0 && x < ix && y < iy && z < iz) src = ((int64_t)z * iy + y) * ix + x;
       }
     }
-    out[v] = val;
+    // channels in groups of kIm2colMaxC: gather a group, transpose, write
+    const int j = threadIdx.x & 31;  // voxel group of 8 inside the tile
+    const int64_t vg = v0 + 8 * j;
+    for (int cb = 0; cb < cip; cb += kIm2colMaxC) {
+      const int cw = cip - cb < kIm2colMaxC ? cip - cb : kIm2colMaxC;
+      for (int c8 = 0; c8 < cw / 8; ++c8) {
+        bf16x8 val;
+        if (src >= 0) {
+          val = *reinterpret_cast<const bf16x8*>(a + src * a_ld + cb + 8 * c8);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) val[e] = (bf16)0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tr[8 * c8 + e][threadIdx.x] = val[e];
+      }
+      __syncthreads();
+      // 2. rows tap * cip + cb + ci, 8 voxels per lane
+      if (vg < ld) {
+        for (int ci = threadIdx.x >> 5; ci < cw; ci += 8) {
+          bf16x8 out;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) out[e] = tr[ci][8 * j + e];
+          *reinterpret_cast<bf16x8*>(xt + ((int64_t)tap * cip + cb + ci) * ld + vg) = out;
+        }
+      }
+      __syncthreads();
+    }
   }
-  (void)kf;
 }
 
 // dT[n][v] = dpre[v][n] for n < cop (rows up to nrows zero), zero padding v >= nv.
@@ -788,9 +812,8 @@ fit_status layer_bwd(fit_precond* p, Acts& a, const DevLayer& L, const bf16* in,
     return FIT_E_DEVICE;
   }
   const int gk = up ? L_PW : sp.kind;
-  hipLaunchKernelGGL(im2colT_kernel, dim3((unsigned)std::min<int64_t>(64, (ld + 255) / 256), (unsigned)M),
-                     dim3(256), 0, s, in, in_ld, cip, gk, bi.X, bi.Y, bi.Z, up ? bi.X : bo.X,
-                     up ? bi.Y : bo.Y, nv_w, M, a.xt, ld);
+  hipLaunchKernelGGL(im2colT_kernel, dim3((unsigned)((ld + 255) / 256), (unsigned)(M / cip)), dim3(256), 0, s,
+                     in, in_ld, cip, gk, bi.X, bi.Y, bi.Z, up ? bi.X : bo.X, up ? bi.Y : bo.Y, nv_w, a.xt, ld);
   FIT_HIP(hipGetLastError());
   hipLaunchKernelGGL(dgradT_kernel, dim3(nblk((int64_t)std::max(nrows, cop) * ld)), dim3(256), 0, s, dpre,
                      cop, sp.cout, up ? 1 : 0, bi.X, bi.Y, nv_w, std::max(nrows, cop), a.dt, ld);
