@@ -161,6 +161,39 @@ def test_full_size_128_cubed_sampled_parity(dtype):
     assert worst <= (1e-12 if dtype == "c128" else 1e-5), worst
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_full_size_256_interconnect_sampled_parity(dtype):
+    """The 256x256x128-cell interconnect (25.6M unknowns) at full size,
+    default launch, in both precisions: sampled nodes, tile seams and the
+    port column checked one by one against the oracle on local crops."""
+    dev = D.interconnect_256(3)
+    g = fit.Grid(dev)
+    npdt = np.complex128 if dtype == "c128" else np.complex64
+    x = rand_c(dev.n_edges, 37, npdt)
+    om = 2 * np.pi * 10e9
+    y = g.matvec(om, _cuda(x)).cpu().numpy().astype(np.complex128)
+    x = x.astype(np.complex128)
+    rng = np.random.default_rng(8)
+    nx, ny, nz = dev.nodes
+    pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz)))
+           for _ in range(80)]
+    pts += [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx // 2, ny // 2, nz // 2), (31, 7, 64), (32, 8, 65)]
+    p0 = dev.ports[0]
+    pts.append((p0.i, p0.j, (p0.k0 + p0.k1) // 2))
+    worst = 0.0
+    for (i, j, k) in pts:
+        sub, off = crop(dev, i, j, k)
+        xs = crop_vector(dev, sub, off, x)
+        ys = O.matvec(sub, om, xs)
+        li, lj, lk = i - off[0], j - off[1], k - off[2]
+        for w in range(3):
+            ref = ys[sub.edge_index(w, li, lj, lk)]
+            got = y[dev.edge_index(w, i, j, k)]
+            scale = max(np.abs(ys).max(), 1e-300)
+            worst = max(worst, abs(got - ref) / scale)
+    assert worst <= (1e-12 if dtype == "c128" else 1e-5), worst
+
+
 def test_autotune_records_a_shape():
     dev = DEVS["layered_pec"]
     g = _grid("layered_pec")

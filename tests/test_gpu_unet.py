@@ -154,3 +154,23 @@ def test_fgmres_with_the_network_tracks_the_oracle():
     _, _, r_plain = O.gmres(O.system_matrix(dev, om), O.rhs(dev, om, src), restart=30, tol=1e-14,
                             maxiter=nit)
     assert abs(r_plain - rc) > 0.1 * rc
+
+
+def test_full_size_family_device_properties():
+    """The 192x192x96-cell family device at full size, the application the
+    benchmark times (c = 16): the output is finite, zero on masked edges,
+    and exactly equivariant to a power-of-two scaling of the input (z = s
+    U(v / s) with s the rms of v, so v -> 2 v gives z -> 2 z bit for bit)."""
+    dev = D.learned_family_device(9000)
+    g = fit.Grid(dev)
+    pre = fit.Precond.create(base_channels=16, seed=1)
+    free = O.free_edges(dev)
+    v = rand_c(dev.n_edges, 41) * free
+    om = 2 * np.pi * 1e10
+    vd = _cuda(v)
+    z1 = pre.apply(g, om, vd).cpu().numpy()
+    z2 = pre.apply(g, om, 2 * vd).cpu().numpy()
+    assert np.all(np.isfinite(z1))
+    assert np.all(z1[~free] == 0)
+    assert np.linalg.norm(z1) > 0
+    np.testing.assert_array_equal(z2, 2 * z1)
