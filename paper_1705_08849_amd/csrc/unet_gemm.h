@@ -126,6 +126,14 @@ struct KCursor {
   int tap, ci;
 };
 
+// Orders LDS stores of one wavefront before loads by other lanes of the same
+// wavefront (a compiler barrier plus wavefront-scope release/acquire fences).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int NT>
 __global__ void __launch_bounds__(256) igemm_kernel(GemmArgs p) {
   constexpr int NS = NT / 16;  // N subtiles per wave
@@ -230,6 +238,36 @@ __global__ void __launch_bounds__(256) igemm_kernel(GemmArgs p) {
   EpiCol col[NS];
 #pragma unroll
   for (int t = 0; t < NS; ++t) col[t] = epi_col(p, n0 + t * 16 + (lane & 15));
+  // bf16 outputs of a full column tile (also the children of a transposed
+  // convolution, 8 channels of one child at a time) go through this
+  // wavefront's LDS rows and leave as 16-byte stores
+  constexpr int kRow = NT + 8;  // halfwords per staged row (16-byte aligned rows)
+  __shared__ bf16 stage[4 * 16 * MS * kRow];
+  const bool packed = p.out == O_BF16 && n0 + NT <= p.N && (p.o_ld & 7) == 0 &&
+                      (!p.up || (p.up_c & 7) == 0) && ((reinterpret_cast<uintptr_t>(p.o16) & 15) == 0);
+  if (packed) {  // uniform over the block; each wavefront uses only its own rows
+    bf16* stg = stage + wave * 16 * MS * kRow;
+#pragma unroll
+    for (int s = 0; s < MS; ++s)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+          float v = acc[s][t][r] + col[t].bias;
+          if (p.relu) v = v > 0.f ? v : 0.f;
+          stg[(16 * s + 4 * (lane >> 4) + r) * kRow + t * 16 + (lane & 15)] = (bf16)v;
+        }
+    wave_sync();
+    for (int q = lane; q < 16 * MS * (NT / 8); q += 64) {
+      const int rloc = q / (NT / 8), c8 = q % (NT / 8);
+      const int64_t row = m_tile + rloc;
+      if (row >= p.M) continue;
+      const EpiCol c = epi_col(p, n0 + 8 * c8);  // 8 channels of one column group (one child)
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(stg + rloc * kRow + 8 * c8);
+      *reinterpret_cast<bf16x8*>(p.o16 + epi_row(p, row) + c.off) = v;
+    }
+    return;
+  }
 #pragma unroll
   for (int s = 0; s < MS; ++s) {
 #pragma unroll
@@ -404,6 +442,39 @@ __global__ void __launch_bounds__(256) conv3_lds_kernel(GemmArgs p) {
   EpiCol col[NS];
 #pragma unroll
   for (int t = 0; t < NS; ++t) col[t] = epi_col(p, n0 + t * 16 + (lane & 15));
+  // bf16 outputs of a full column tile go through LDS (the halo tile is free
+  // once every wavefront has left its K loop) and leave as 16-byte stores of
+  // 8 channels instead of 2-byte stores
+  constexpr int kRow = NT + 8;  // halfwords per staged row (16-byte aligned rows)
+  if constexpr (4 * 64 * kRow * 2 <= (int)sizeof(tile)) {
+    const bool packed = p.out == O_BF16 && !p.up && n0 + NT <= p.N && (p.o_ld & 7) == 0 &&
+                        ((reinterpret_cast<uintptr_t>(p.o16) & 15) == 0);
+    if (packed) {  // uniform over the block
+      __syncthreads();
+      bf16* stg = reinterpret_cast<bf16*>(tile) + wave * 64 * kRow;
+#pragma unroll
+      for (int s = 0; s < MS; ++s)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int t = 0; t < NS; ++t) {
+            float v = acc[s][t][r] + col[t].bias;
+            if (p.relu) v = v > 0.f ? v : 0.f;
+            stg[(16 * s + 4 * (lane >> 4) + r) * kRow + t * 16 + (lane & 15)] = (bf16)v;
+          }
+      // each wavefront reads back only its own rows: no block barrier needed
+      wave_sync();
+      for (int q = lane; q < 64 * (NT / 8); q += 64) {
+        const int row = q / (NT / 8), c8 = q % (NT / 8);
+        const int rl = wave * 64 + row;
+        const int x = bx0 + rl % kBrX, y = by0 + (rl / kBrX) % kBrY, z = bz0 + rl / (kBrX * kBrY);
+        if (x >= p.ix || y >= p.iy || z >= p.iz) continue;
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(stg + row * kRow + 8 * c8);
+        *reinterpret_cast<bf16x8*>(p.o16 + (((int64_t)z * p.iy + y) * p.ix + x) * p.o_ld + n0 + 8 * c8) = v;
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int s = 0; s < MS; ++s) {
 #pragma unroll
