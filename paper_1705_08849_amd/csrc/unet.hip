@@ -667,6 +667,10 @@ fit_status gemm(const GemmArgs& g, int64_t n_cols, hipStream_t s, int splits = 1
   // 3x3x3 convolutions with 8, 16, 32 or 64 input channels take the
   // LDS-staged kernel
   const bool lds_cin = a.cin == 8 || a.cin == 16 || a.cin == 32 || a.cin == 64;
+  // bf16 outputs whose 8-channel groups are 16-byte aligned take the kernels'
+  // packed-store instantiation
+  const bool pk = a.out == O_BF16 && (a.o_ld & 7) == 0 && (!a.up || (a.up_c & 7) == 0) &&
+                  (reinterpret_cast<uintptr_t>(a.o16) & 15) == 0;
   if (a.gather == G_CONV3 && splits == 1 && lds_cin && a.K == 27LL * a.cin && a.ox == a.ix && a.oy == a.iy &&
       a.M == (int64_t)a.ix * a.iy * a.iz && !a.up) {
     const int64_t nb = (int64_t)((a.ix + kBrX - 1) / kBrX) * ((a.iy + kBrY - 1) / kBrY) * ((a.iz + kBrZ - 1) / kBrZ);
@@ -676,8 +680,13 @@ fit_status gemm(const GemmArgs& g, int64_t n_cols, hipStream_t s, int splits = 1
     while (ntc > 16 && nb * ((n_cols + ntc - 1) / ntc) < 1024) ntc /= 2;
     const dim3 grid((unsigned)nb, (unsigned)((n_cols + ntc - 1) / ntc), 1);
     const int tok = prof_begin(s);
-#define CONV(NT, CI) \
-  if (ntc == NT && a.cin == CI) hipLaunchKernelGGL((conv3_lds_kernel<NT, CI>), grid, dim3(256), 0, s, a);
+#define CONV(NT, CI)                                                                   \
+  if (ntc == NT && a.cin == CI) {                                                      \
+    if (pk)                                                                            \
+      hipLaunchKernelGGL((conv3_lds_kernel<NT, CI, true>), grid, dim3(256), 0, s, a);  \
+    else                                                                               \
+      hipLaunchKernelGGL((conv3_lds_kernel<NT, CI, false>), grid, dim3(256), 0, s, a); \
+  }
     CONV(16, 8) CONV(16, 16) CONV(16, 32) CONV(16, 64) CONV(32, 8) CONV(32, 16) CONV(32, 32) CONV(32, 64)
     CONV(64, 8) CONV(64, 16) CONV(64, 32) CONV(64, 64)
 #undef CONV
@@ -687,12 +696,15 @@ fit_status gemm(const GemmArgs& g, int64_t n_cols, hipStream_t s, int splits = 1
   }
   const dim3 grid((unsigned)((a.M + 127) / 128), (unsigned)((n_cols + nt - 1) / nt), (unsigned)splits);
   const int tok = prof_begin(s);
-  if (nt == 16)
-    hipLaunchKernelGGL(igemm_kernel<16>, grid, dim3(256), 0, s, a);
-  else if (nt == 32)
-    hipLaunchKernelGGL(igemm_kernel<32>, grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(igemm_kernel<64>, grid, dim3(256), 0, s, a);
+#define IGEMM(NT)                                                                  \
+  if (nt == NT) {                                                                  \
+    if (pk)                                                                        \
+      hipLaunchKernelGGL((igemm_kernel<NT, true>), grid, dim3(256), 0, s, a);      \
+    else                                                                           \
+      hipLaunchKernelGGL((igemm_kernel<NT, false>), grid, dim3(256), 0, s, a);     \
+  }
+  IGEMM(16) IGEMM(32) IGEMM(64)
+#undef IGEMM
   FIT_HIP(hipGetLastError());
   prof_end(tok, s, "unet_igemm_bf16");
   return FIT_OK;

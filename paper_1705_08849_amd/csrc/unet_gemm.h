@@ -134,7 +134,10 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int NT>
+// PK: the launch writes bf16 outputs and may take the packed (LDS-staged,
+// 16-byte) store; a separate instantiation, so that the K loop of every other
+// launch compiles exactly as without it.
+template <int NT, bool PK>
 __global__ void __launch_bounds__(256) igemm_kernel(GemmArgs p) {
   constexpr int NS = NT / 16;  // N subtiles per wave
   constexpr int MS = 2;        // 16-row M subtiles per wave
@@ -242,31 +245,33 @@ __global__ void __launch_bounds__(256) igemm_kernel(GemmArgs p) {
   // convolution, 8 channels of one child at a time) go through this
   // wavefront's LDS rows and leave as 16-byte stores
   constexpr int kRow = NT + 8;  // halfwords per staged row (16-byte aligned rows)
-  __shared__ bf16 stage[4 * 16 * MS * kRow];
-  const bool packed = p.out == O_BF16 && n0 + NT <= p.N && (p.o_ld & 7) == 0 &&
-                      (!p.up || (p.up_c & 7) == 0) && ((reinterpret_cast<uintptr_t>(p.o16) & 15) == 0);
-  if (packed) {  // uniform over the block; each wavefront uses only its own rows
-    bf16* stg = stage + wave * 16 * MS * kRow;
+  if constexpr (PK) {
+    __shared__ bf16 stage[4 * 16 * MS * kRow];
+    const bool packed = p.out == O_BF16 && n0 + NT <= p.N && (p.o_ld & 7) == 0 &&
+                        (!p.up || (p.up_c & 7) == 0) && ((reinterpret_cast<uintptr_t>(p.o16) & 15) == 0);
+    if (packed) {  // uniform over the block; each wavefront uses only its own rows
+      bf16* stg = stage + wave * 16 * MS * kRow;
 #pragma unroll
-    for (int s = 0; s < MS; ++s)
+      for (int s = 0; s < MS; ++s)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int t = 0; t < NS; ++t) {
-          float v = acc[s][t][r] + col[t].bias;
-          if (p.relu) v = v > 0.f ? v : 0.f;
-          stg[(16 * s + 4 * (lane >> 4) + r) * kRow + t * 16 + (lane & 15)] = (bf16)v;
-        }
-    wave_sync();
-    for (int q = lane; q < 16 * MS * (NT / 8); q += 64) {
-      const int rloc = q / (NT / 8), c8 = q % (NT / 8);
-      const int64_t row = m_tile + rloc;
-      if (row >= p.M) continue;
-      const EpiCol c = epi_col(p, n0 + 8 * c8);  // 8 channels of one column group (one child)
-      const bf16x8 v = *reinterpret_cast<const bf16x8*>(stg + rloc * kRow + 8 * c8);
-      *reinterpret_cast<bf16x8*>(p.o16 + epi_row(p, row) + c.off) = v;
+          for (int t = 0; t < NS; ++t) {
+            float v = acc[s][t][r] + col[t].bias;
+            if (p.relu) v = v > 0.f ? v : 0.f;
+            stg[(16 * s + 4 * (lane >> 4) + r) * kRow + t * 16 + (lane & 15)] = (bf16)v;
+          }
+      wave_sync();
+      for (int q = lane; q < 16 * MS * (NT / 8); q += 64) {
+        const int rloc = q / (NT / 8), c8 = q % (NT / 8);
+        const int64_t row = m_tile + rloc;
+        if (row >= p.M) continue;
+        const EpiCol c = epi_col(p, n0 + 8 * c8);  // 8 channels of one column group (one child)
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(stg + rloc * kRow + 8 * c8);
+        *reinterpret_cast<bf16x8*>(p.o16 + epi_row(p, row) + c.off) = v;
+      }
+      return;
     }
-    return;
   }
 #pragma unroll
   for (int s = 0; s < MS; ++s) {
@@ -313,7 +318,7 @@ __device__ __forceinline__ int conv_slot(unsigned h, unsigned c) {
   return (int)(h * C8 + (c ^ ((h / per_line) & (C8 - 1))));
 }
 
-template <int NT, int CIN>
+template <int NT, int CIN, bool PK>
 __global__ void __launch_bounds__(256) conv3_lds_kernel(GemmArgs p) {
   constexpr int NS = NT / 16;
   constexpr int MS = 4;
@@ -446,7 +451,7 @@ __global__ void __launch_bounds__(256) conv3_lds_kernel(GemmArgs p) {
   // once every wavefront has left its K loop) and leave as 16-byte stores of
   // 8 channels instead of 2-byte stores
   constexpr int kRow = NT + 8;  // halfwords per staged row (16-byte aligned rows)
-  if constexpr (4 * 64 * kRow * 2 <= (int)sizeof(tile)) {
+  if constexpr (PK && 4 * 64 * kRow * 2 <= (int)sizeof(tile)) {
     const bool packed = p.out == O_BF16 && !p.up && n0 + NT <= p.N && (p.o_ld & 7) == 0 &&
                         ((reinterpret_cast<uintptr_t>(p.o16) & 15) == 0);
     if (packed) {  // uniform over the block
