@@ -87,6 +87,8 @@ LayerMats mats_of(const Spec& s) {
 }
 
 int ntile(int64_t n) { return n <= 16 ? 16 : (n <= 32 ? 32 : 64); }
+// Most K splits of a weight-gradient GEMM (its fp32 partials are splits x M x N).
+constexpr int64_t kMaxSplits = 64;
 int64_t rows_pad(int64_t n) { const int t = ntile(n); return (n + t - 1) / t * t; }
 
 // ---------------------------------------------------------------------------
@@ -637,7 +639,7 @@ fit_status make_acts(fit_precond* p, int X, int Y, int Z, bool grads, std::uniqu
       const int64_t nrows = std::max<int64_t>(rows_pad(ncols), pad8(s.cout));
       xt = std::max(xt, m * ld);
       dt = std::max(dt, nrows * ld);
-      pt = std::max(pt, 16 * m * ncols);
+      pt = std::max(pt, kMaxSplits * m * ncols);
     }
     a->xt = dalloc<bf16>(*a, xt, &st);
     a->dt = dalloc<bf16>(*a, dt, &st);
@@ -830,7 +832,12 @@ fit_status layer_bwd(fit_precond* p, Acts& a, const DevLayer& L, const bf16* in,
   hipLaunchKernelGGL(dgradT_kernel, dim3(nblk((int64_t)std::max(nrows, cop) * ld)), dim3(256), 0, s, dpre,
                      cop, sp.cout, up ? 1 : 0, bi.X, bi.Y, nv_w, std::max(nrows, cop), a.dt, ld);
   FIT_HIP(hipGetLastError());
-  int splits = (int)std::min<int64_t>(16, std::max<int64_t>(1, ld / 2048));
+  // split K (the voxels) so that the launch has about 1,024 workgroups, each
+  // summing at least 256 voxels; the split count depends on the shapes only,
+  // so the summation order is fixed
+  const int64_t tiles = ((M + 127) / 128) * ((ncols + ntile(ncols) - 1) / ntile(ncols));
+  int splits = (int)std::min<int64_t>(std::min<int64_t>(kMaxSplits, std::max<int64_t>(1, ld / 256)),
+                                      std::max<int64_t>(1, (1024 + tiles - 1) / tiles));
   while (splits > 1 && (int64_t)splits * M * ncols > a.part_bytes) --splits;
   {
     GemmArgs g{};
