@@ -239,14 +239,20 @@ __global__ void dgradT_kernel(const bf16* dpre, int cop, int cout, int up, int o
   }
 }
 
-// Sum the split-K partials into the canonical gradient, and the bias
-// gradient from the rows of dT (one block per output).
-__global__ void reduce_dw_kernel(const float* part, int splits, int64_t M, int64_t N, int kind, int taps,
-                                 int cin, int cout, float scale, float* gw) {
+// Sum the split-K partials into the canonical gradient.  A block of 256
+// threads owns 64 consecutive outputs; its four wavefronts sum interleaved
+// quarters of the splits (lanes read consecutive columns) and the quarters
+// are added in a fixed order, so the result does not depend on timing.
+__global__ void __launch_bounds__(256) reduce_dw_kernel(const float* part, int splits, int64_t M, int64_t N,
+                                                        int kind, int taps, int cin, int cout, float scale,
+                                                        float* gw) {
+  __shared__ float quarter[4][64];
   const int cip = pad8(cin);
   const int64_t total = (int64_t)taps * cin * cout;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  float s = 0.f;
+  if (q < total) {
     const int co = (int)(q % cout), ci = (int)((q / cout) % cin), t = (int)(q / ((int64_t)cout * cin));
     int64_t row, col;
     if (kind == L_UP2) {
@@ -256,10 +262,12 @@ __global__ void reduce_dw_kernel(const float* part, int splits, int64_t M, int64
       row = (int64_t)t * cip + ci;
       col = co;
     }
-    float s = 0.f;
-    for (int sp = 0; sp < splits; ++sp) s += part[((int64_t)sp * M + row) * N + col];
-    gw[q] += scale * s;
+    for (int sp = g; sp < splits; sp += 4) s += part[((int64_t)sp * M + row) * N + col];
   }
+  quarter[g][lane] = s;
+  __syncthreads();
+  if (g == 0 && q < total)
+    gw[q] += scale * (((quarter[0][lane] + quarter[1][lane]) + quarter[2][lane]) + quarter[3][lane]);
 }
 
 __global__ void __launch_bounds__(1024) bias_grad_kernel(const bf16* dt, int64_t ld, int cout, int up,
@@ -856,8 +864,8 @@ fit_status layer_bwd(fit_precond* p, Acts& a, const DevLayer& L, const bf16* in,
     if (st != FIT_OK) return st;
   }
   const int64_t nw = (int64_t)sp.taps * sp.cin * sp.cout;
-  hipLaunchKernelGGL(reduce_dw_kernel, dim3(nblk(nw)), dim3(256), 0, s, a.part, splits, M, ncols, sp.kind,
-                     sp.taps, sp.cin, sp.cout, scale, p->G + L.w_off);
+  hipLaunchKernelGGL(reduce_dw_kernel, dim3((unsigned)((nw + 63) / 64)), dim3(256), 0, s, a.part, splits, M,
+                     ncols, sp.kind, sp.taps, sp.cin, sp.cout, scale, p->G + L.w_off);
   FIT_HIP(hipGetLastError());
   hipLaunchKernelGGL(bias_grad_kernel, dim3(sp.cout), dim3(1024), 0, s, a.dt, ld, sp.cout, up ? 1 : 0, scale,
                      p->G + L.b_off);
