@@ -398,7 +398,7 @@ def main():
 
     mv_us = mean_us(lambda: g.matvec(omega, xv, yv, scaling="none"))
     mv_bytes = n_nodes * 6 * 16 + n_cells
-    # the box's device copy bandwidth on vectors of the same size, as a
+    # this device's copy bandwidth on vectors of the same size, as a
     # second reference besides the 8 TB/s peak
     cp_us = mean_us(lambda: yv.copy_(xv))
     copy_gbs = 2 * xv.numel() * 16 / cp_us / 1e3
