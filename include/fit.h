@@ -250,6 +250,24 @@ fit_status fit_sweep(struct fit_grid *const *grids, int ngrids, const double *om
 fit_status fit_port_voltages(const struct fit_grid *g, const void *x_dev, int nvec,
                              double *out_host, void *stream);
 
+/* Network parameters of the ports (Sec. IV port model: each lumped port is a
+ * 1 A source in parallel with its internal impedance z0, which the port's
+ * edges carry as conductance).  Host-only and synchronous.
+ *   zl:    host, nports x nports complex128 (2 doubles each), row-major: the
+ *          loaded impedance zl[p][q] = -u_p for a unit current at port q
+ *          with every port loaded by z0 (u = fit_port_voltages of that
+ *          solve; the minus sign because an edge voltage integrates E from
+ *          the ground end up).
+ *   z_out: NULL or host nports x nports complex128: the network's own
+ *          impedance matrix with the loads removed, Z = (zl^-1 - I/z0)^-1.
+ *   s_out: NULL or host nports x nports complex128: the scattering matrix
+ *          for reference impedance z0, S = (Z - z0 I)(Z + z0 I)^-1, which
+ *          equals 2 zl / z0 - I.
+ * FIT_E_INVALID (nothing written) for nports outside [1, 64], z0 <= 0, a NULL
+ * or non-finite zl, or, when z_out is asked for, a singular zl or
+ * zl^-1 - I/z0. */
+fit_status fit_port_network(int nports, double z0, const double *zl, double *z_out, double *s_out);
+
 /* ---- stencil launch shapes and the autotuner ------------------------------
  * A workgroup of tx x ty threads covers tx x ty node columns -- the
  * (tx-2) x (ty-2) columns it outputs plus a one-node halo ring -- and marches

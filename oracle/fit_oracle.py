@@ -290,6 +290,34 @@ def port_voltages(dev, x: np.ndarray) -> np.ndarray:
                     dtype=np.complex128)
 
 
+def loaded_impedance(dev, omega: float) -> np.ndarray:
+    """Loaded port impedance matrix: column q is ``-u`` (port voltages,
+    Sec. IV probe rule) of the direct solve driven by a unit current at
+    port q, every port loaded by its internal impedance (reading of the
+    lumped port as a Norton source)."""
+    n = len(dev.ports)
+    zl = np.zeros((n, n), dtype=np.complex128)
+    for q in range(n):
+        jsrc = np.zeros(dev.n_edges)
+        jsrc[dev.port_edges(q)] = 1.0
+        zl[:, q] = -port_voltages(dev, solve_direct(dev, omega, jsrc))
+    return zl
+
+
+def port_network(zl: np.ndarray, z0: float):
+    """Network parameters from the loaded impedance matrix, by their
+    definitions: the ports' own admittance is the loaded one minus the
+    loads, ``Y = zl^-1 - I/z0``, ``Z = Y^-1``, and the scattering matrix for
+    reference impedance z0 is ``S = (Z - z0 I)(Z + z0 I)^-1``.  Returns
+    ``(Z, S)``."""
+    n = zl.shape[0]
+    eye = np.eye(n)
+    y = np.linalg.inv(zl) - eye / z0
+    z = np.linalg.inv(y)
+    s = (z - z0 * eye) @ np.linalg.inv(z + z0 * eye)
+    return z, s
+
+
 def solve_direct(dev, omega: float, jsrc: np.ndarray) -> np.ndarray:
     """Sparse direct solve of ``A x = b``; returns ``x`` on all edges."""
     a = system_matrix(dev, omega).tocsc()

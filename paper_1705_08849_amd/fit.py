@@ -123,6 +123,8 @@ _SIGS = [
                             C.POINTER(C.c_double), C.POINTER(C.c_void_p), C.POINTER(SolveInfo)]),
     ("fit_port_voltages", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_double),
                                     C.c_void_p]),
+    ("fit_port_network", C.c_int, [C.c_int, C.c_double, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("fit_precond_train", C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_double),
                                     C.c_int, C.POINTER(PrecondCfg), C.POINTER(C.c_void_p)]),
     ("fit_precond_create", C.c_int, [C.POINTER(PrecondCfg), C.c_int, C.POINTER(C.c_void_p)]),
@@ -328,6 +330,23 @@ class Grid:
               "fit_port_voltages")
         a = np.frombuffer(out, dtype=np.float64)[: 2 * n * nvec].copy()
         return a.view(np.complex128).reshape(nvec, n)
+
+
+def port_network(zl, z0: float = 50.0):
+    """Unloaded impedance matrix Z and scattering matrix S of the ports from
+    the loaded impedance matrix ``zl`` (``zl[p, q] = -u_p`` for a unit
+    current at port q); see ``fit_port_network``.  Returns ``(z, s)``."""
+    a = np.ascontiguousarray(np.asarray(zl, dtype=np.complex128))
+    n = a.shape[0] if a.ndim == 2 else 0
+    if a.ndim != 2 or a.shape[1] != n:
+        raise ValueError("port_network: zl must be a square matrix")
+    zin = a.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
+    zo = (C.c_double * (2 * n * n))()
+    so = (C.c_double * (2 * n * n))()
+    check(lib().fit_port_network(n, float(z0), zin, zo, so), "fit_port_network")
+    z = np.frombuffer(zo, dtype=np.float64).copy().view(np.complex128).reshape(n, n)
+    s_ = np.frombuffer(so, dtype=np.float64).copy().view(np.complex128).reshape(n, n)
+    return z, s_
 
 
 def sweep(grids: Sequence[Grid], omegas: Sequence[float], sources, tol: float = 1e-8,

@@ -108,3 +108,32 @@ def test_batched_and_sweep_argument_checks():
     assert L.fit_sweep(gh, 1, om, 2, src, 1, 2.0, None, None, None, None) == fit.E_INVALID
     bad = (C.c_double * 2)(1e9, -1.0)
     assert L.fit_sweep(gh, 1, bad, 2, src, 1, 1e-8, None, None, None, None) == fit.E_INVALID
+
+
+def test_port_network_host_matches_the_oracle():
+    """fit_port_network (host code in the library) against the oracle's
+    definitions on random loaded impedance matrices of 1 to 6 ports."""
+    from oracle import fit_oracle as O
+    rng = np.random.default_rng(11)
+    for n in (1, 2, 4, 6):
+        zl = 40 * (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) + 30 * np.eye(n)
+        z, s = fit.port_network(zl, 50.0)
+        z_ref, s_ref = O.port_network(zl, 50.0)
+        np.testing.assert_allclose(z, z_ref, rtol=1e-10, atol=1e-10 * abs(z_ref).max())
+        np.testing.assert_allclose(s, s_ref, rtol=1e-10, atol=1e-10 * abs(s_ref).max())
+
+
+def test_port_network_rejects_bad_arguments_and_writes_nothing():
+    L = fit.lib()
+    buf = (C.c_double * 8)(*([7.0] * 8))
+    out = (C.c_double * 8)(*([-3.0] * 8))
+    assert L.fit_port_network(0, 50.0, buf, out, out) == fit.E_INVALID
+    assert L.fit_port_network(2, 0.0, buf, out, out) == fit.E_INVALID
+    assert L.fit_port_network(65, 50.0, buf, out, out) == fit.E_INVALID
+    assert L.fit_port_network(2, 50.0, None, out, out) == fit.E_INVALID
+    # all-equal entries: zl is singular, so the unloaded Z does not exist
+    assert L.fit_port_network(2, 50.0, buf, out, None) == fit.E_INVALID
+    assert list(out) == [-3.0] * 8
+    # S alone needs no inversion
+    assert L.fit_port_network(2, 50.0, buf, None, out) == fit.OK
+    assert abs(out[0] - (2 * 7.0 / 50.0 - 1.0)) < 1e-15 and abs(out[2] - 2 * 7.0 / 50.0) < 1e-15

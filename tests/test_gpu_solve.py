@@ -192,6 +192,29 @@ def test_port_voltages_and_reciprocity():
     assert z[0, 0].real >= 0 and z[1, 1].real >= 0
 
 
+def test_port_network_from_gpu_solves_matches_the_oracle():
+    """Loaded impedance from GPU solves (one per port, true residual 1e-10)
+    -> fit_port_network -> unloaded Z and S, against the oracle's direct
+    solves and definitions.  The bound follows the solve tolerance: a true
+    residual of 1e-10 on this graded device leaves a forward error of the
+    port voltages far below 1e-5 relative (the network is nearly lossless:
+    the largest singular value of S is 1 - 1e-7, so passivity is checked to
+    the same 1e-5 scale)."""
+    dev = _small_device()
+    g = fit.Grid(dev)
+    om = 2 * np.pi * 9e9
+    zl = np.zeros((2, 2), complex)
+    for q in range(2):
+        x, info = g.solve(om, _cuda(D.port_source(dev, q)), tol=1e-10)
+        assert info["true_relres"] <= 1e-10
+        zl[:, q] = -g.port_voltages(x)[0]
+    z, s = fit.port_network(zl, 50.0)
+    z_ref, s_ref = O.port_network(O.loaded_impedance(dev, om), 50.0)
+    np.testing.assert_allclose(z, z_ref, rtol=1e-5, atol=1e-5 * abs(z_ref).max())
+    np.testing.assert_allclose(s, s_ref, rtol=0, atol=1e-5)
+    assert np.linalg.svd(s, compute_uv=False).max() <= 1.0 + 1e-5  # passive
+
+
 def test_cavity_eigen_check_by_inverse_iteration():
     """TE101/TE011/TE110 of the 16 mm cavity from GPU solves: shifted inverse
     iteration at 13 GHz, then the Rayleigh quotient x^T K x / x^T M_eps x with

@@ -407,6 +407,39 @@ def test_reciprocity_and_passivity_of_two_port():
     assert z[0, 0].real >= 0 and z[1, 1].real >= 0
 
 
+def test_scattering_matrix_equals_its_closed_form_in_the_loaded_impedance():
+    """With Norton ports loaded by z0, S = (Z - z0)(Z + z0)^-1 computed from
+    its definition (two inversions to Z, one more for S) equals
+    2 zl / z0 - I: on the two-port device and on random matrices."""
+    dev = D.layered_device(12, 10, 6, n_layers=2, n_strips=2, n_ports=2, seed=4)
+    zl = O.loaded_impedance(dev, 2 * np.pi * 6e9)
+    rng = np.random.default_rng(3)
+    for m in [zl] + [rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)) for n in (1, 3, 5)]:
+        _, s = O.port_network(m, 50.0)
+        np.testing.assert_allclose(s, 2 * m / 50.0 - np.eye(m.shape[0]), rtol=0, atol=1e-10 * max(1, abs(s).max()))
+
+
+@pytest.mark.parametrize("z, s_ref", [(50.0, 0.0), (150.0, 0.5), (50.0 / 3, -0.5), (50j, 1j)])
+def test_one_port_network_round_trip_and_reflection(z, s_ref):
+    """A one-port of impedance z loaded by z0 = 50 Ohm shows zl = z || z0;
+    the oracle recovers z, and S = (z - z0)/(z + z0) (0 matched, +-1/2,
+    a pure reactance j z0 reflects with S = j)."""
+    zl = np.array([[1.0 / (1.0 / z + 1.0 / 50.0)]], dtype=np.complex128)
+    zz, s = O.port_network(zl, 50.0)
+    np.testing.assert_allclose(zz[0, 0], z, rtol=1e-12)
+    np.testing.assert_allclose(s[0, 0], s_ref, atol=1e-12)
+
+
+def test_two_port_network_is_reciprocal_and_passive():
+    """Z and S of the lossy two-port are symmetric (complex symmetry of A)
+    and S is contractive (no singular value above 1: the device absorbs)."""
+    dev = D.layered_device(12, 10, 6, n_layers=2, n_strips=2, n_ports=2, seed=4)
+    z, s = O.port_network(O.loaded_impedance(dev, 2 * np.pi * 6e9), 50.0)
+    assert abs(z[0, 1] - z[1, 0]) <= 1e-8 * abs(z).max()
+    assert abs(s[0, 1] - s[1, 0]) <= 1e-9
+    assert np.linalg.svd(s, compute_uv=False).max() <= 1.0 + 1e-12
+
+
 def test_tiny_cavity_case_bicgstab_reaches_1e8():
     dev, om, j = D.tiny_cavity_case()
     a = O.system_matrix(dev, om)
