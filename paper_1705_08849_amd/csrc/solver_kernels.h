@@ -501,7 +501,12 @@ __device__ __forceinline__ void pcocg_rupdate_otf_body(const GridView& g, double
   const int ncol = g.nx * g.ny;
   const int nbxy = (ncol + 255) / 256, nbz = (g.nz + ZC - 1) / ZC;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int ch = bid; ch < nbxy * nbz; ch += nblk) {
+  // items run from the top z-chunk down: the operator step before this
+  // kernel finishes with the top planes (its tiles run bottom to top), so
+  // their r and q are still in the last-level cache, and this kernel ends
+  // at the bottom planes, where the next operator step starts reading r
+  for (int it = bid; it < nbxy * nbz; it += nblk) {
+    const int ch = nbxy * nbz - 1 - it;
     const int c = (ch % nbxy) * 256 + (int)threadIdx.x;
     if (c >= ncol) continue;
     const int k0 = (ch / nbxy) * ZC, k1 = min(k0 + ZC, g.nz);

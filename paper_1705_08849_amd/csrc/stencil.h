@@ -26,8 +26,11 @@
 //    staged in registers one step ahead and its raw data prefetched two.
 //  * Each z-chunk recomputes one plane of facets below it (warm-up), so HBM
 //    reads per node are (1 + 1/ZC) times the block's halo overhead, which
-//    neighbouring tiles scheduled on the same XCD mostly find in L2
-//    (XCD-aware block order).
+//    neighbouring tiles mostly find in L2 or the last-level cache.
+//    Single-system launches run the tiles in plain order (consecutive tiles
+//    round-robin over the XCDs, so the whole device works on one compact
+//    band of the grid, which measured faster than giving each XCD its own
+//    contiguous range); batched launches use the XCD-aware order below.
 //  * Krylov vector updates and reductions are fused through the Op policy:
 //    the input may be produced on the fly from several vectors (and written
 //    back for owned nodes), and the output may feed fused dot products.
@@ -436,7 +439,7 @@ struct TileShape {
   int tx, ty, zc;
 };
 
-inline StencilLaunch make_launch(const GridView& g, TileShape t, double omega, bool xcd = true) {
+inline StencilLaunch make_launch(const GridView& g, TileShape t, double omega, bool xcd = false) {
   StencilLaunch L;
   L.nbx = (g.nx + t.tx - 3) / (t.tx - 2);
   L.nby = (g.ny + t.ty - 3) / (t.ty - 2);
