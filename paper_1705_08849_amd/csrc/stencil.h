@@ -30,7 +30,9 @@
 //    Single-system launches run the tiles in plain order (consecutive tiles
 //    round-robin over the XCDs, so the whole device works on one compact
 //    band of the grid, which measured faster than giving each XCD its own
-//    contiguous range); batched launches use the XCD-aware order below.
+//    contiguous range); so do the multi-system launches of a sweep, while
+//    the batched operator (one grid, several vectors) uses the XCD-aware
+//    order below.
 //  * Krylov vector updates and reductions are fused through the Op policy:
 //    the input may be produced on the fly from several vectors (and written
 //    back for owned nodes), and the output may feed fused dot products.
@@ -397,9 +399,8 @@ __global__ void __launch_bounds__(BX* BY)
 }
 
 // Several operator applications in one launch (systems of a sweep, possibly
-// on different grids): item s owns the logical blocks [block0, block0+nblk).
-// The XCD-aware order runs over the whole launch, so a system's neighbouring
-// tiles still share an XCD.
+// on different grids): item s owns the logical blocks [block0, block0+nblk),
+// found from the workgroup id by binary search.
 template <class Op>
 struct MultiItem {
   GridView g;
@@ -411,7 +412,7 @@ struct MultiItem {
 template <class T, int BX, int BY, int MODE, class Op>
 __global__ void __launch_bounds__(BX* BY)
     stencil_multi_kernel(const MultiItem<Op>* __restrict__ items, int nitems) {
-  const int gb = xcd_remap(blockIdx.x, gridDim.x);
+  const int gb = (int)blockIdx.x;  // plain order, as for single-system launches
   int lo = 0, hi = nitems - 1;
   while (lo < hi) {  // last item whose block0 <= gb
     const int mid = (lo + hi + 1) >> 1;
