@@ -500,19 +500,27 @@ def gmres(a, b, restart=30, tol=1e-8, maxiter=100000, precond=None, x0=None):
 # Generalised eigenproblem of the lossless cavity (Sec. IV, first check).
 # ---------------------------------------------------------------------------
 
-def cavity_eigenfrequencies(dev, k: int = 6, sigma_f: float = None):
-    """Smallest non-zero resonance frequencies (Hz) of ``K e = omega^2 M_eps e``
-    on free edges.  Dense for small grids, shift-invert otherwise."""
+def cavity_omega2(dev) -> np.ndarray:
+    """Every generalised eigenvalue ``omega^2`` [rad^2/s^2] of
+    ``K e = omega^2 M_eps e`` on the free edges of a lossless device, in
+    ascending order, the gradient null space included (one zero per interior
+    node potential).  Dense: for grids of at most a few thousand free edges."""
+    import scipy.linalg as sla
     f = free_edges(dev)
     kk = stiffness(dev)[f][:, f]
     m_eps, _ = edge_materials(dev)
-    m = m_eps[f].real
-    if f.sum() <= 4000 and sigma_f is None:
-        import scipy.linalg as sla
-        lam = sla.eigh(kk.toarray(), np.diag(m), eigvals_only=True)
-        return lam
+    return np.sort(sla.eigh(kk.toarray(), np.diag(m_eps[f].real), eigvals_only=True))
+
+
+def cavity_eigenfrequencies(dev, k: int = 6, sigma_f: float = 1e9) -> np.ndarray:
+    """The ``k`` resonance frequencies [Hz] of ``K e = omega^2 M_eps e`` on
+    the free edges closest to ``sigma_f`` [Hz] (shift-invert Lanczos), in
+    ascending order."""
     import scipy.sparse.linalg as ssl
+    f = free_edges(dev)
+    kk = stiffness(dev)[f][:, f]
+    m_eps, _ = edge_materials(dev)
     sig = (2 * np.pi * sigma_f) ** 2
-    lam = ssl.eigsh(kk.tocsc(), k=k, M=sp.diags(m).tocsc(), sigma=sig,
+    lam = ssl.eigsh(kk.tocsc(), k=k, M=sp.diags(m_eps[f].real).tocsc(), sigma=sig,
                     which="LM", return_eigenvectors=False)
     return np.sort(np.sqrt(np.abs(lam)) / (2 * np.pi))

@@ -28,21 +28,24 @@ namespace fit {
 template <class T>
 struct BiVecs {
   T *x, *r, *rh, *p[2], *v[2], *s, *t;
+  T* xb = nullptr;  // BiCGStab: the iterate with the smallest residual seen at a poll
 };
 
 template <class T>
 static fit_status bicgstab(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int check_every,
                            double hscale, double* hist_dev, int hist_len, int use_graph,
-                           int* done, int* iters, double* rr_out) {
+                           uint64_t shadow_seed, int* done, int* iters, double* rr_out) {
   const int64_t ne = c.g->ne;
   fit_status st;
   if ((st = vzero(c, V.x, ne)) != FIT_OK) return st;
   if ((st = vzero(c, V.p[0], ne)) != FIT_OK) return st;
   if ((st = vzero(c, V.v[0], ne)) != FIT_OK) return st;
-  // Shadow vector: dense pseudo-random on the free edges.  (The textbook
-  // choice r_hat = r_0 collapses for lumped-port sources: r_0 lives on a
-  // handful of edges and <r_hat, r_k> soon vanishes relative to |r_k|.)
-  if ((st = xform<T, T, XF_SHADOW>(c, false, false, V.r, V.rh, 1.0, false)) != FIT_OK) return st;
+  // Shadow vector: dense pseudo-random on the free edges, a fresh seed for
+  // every restart.  (The textbook choice r_hat = r_0 collapses for
+  // lumped-port sources: r_0 lives on a handful of edges and <r_hat, r_k>
+  // soon vanishes relative to |r_k|.)
+  if ((st = xform<T, T, XF_SHADOW>(c, false, false, V.r, V.rh, 1.0, false, shadow_seed)) != FIT_OK)
+    return st;
   hipLaunchKernelGGL(dot_kernel<T>, dim3(pw_blocks(ne)), dim3(256), 0, c.s, V.rh, V.r, ne, c.red,
                      c.part, c.cnt);
   FIT_HIP(hipGetLastError());
@@ -129,6 +132,9 @@ static fit_status bicgstab(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, i
   int best_at = 0;
   bool stalled = false;
   const int stall_window = sizeof(T) == 4 ? 1500 : 6000;
+  // smallest recursive residual seen at a poll, and whether V.xb holds it
+  double kept_rr = r0;
+  bool kept = false;
   for (;;) {
     if (use_graph) {
       hipError_t he = hipGraphLaunch(gexec, c.s);
@@ -146,6 +152,12 @@ static fit_status bicgstab(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, i
     c.matvecs += 2 * (c.h_bst->iter - last_iter);
     last_iter = c.h_bst->iter;
     if (c.h_bst->done != kRunning) break;
+    if (V.xb && std::isfinite(c.h_bst->rr) && c.h_bst->rr < kept_rr) {
+      if ((ret = vcopy(c, V.x, V.xb, ne)) != FIT_OK) break;
+      c.bytes += (double)ne * sizeof(T) * 4;
+      kept_rr = c.h_bst->rr;
+      kept = true;
+    }
     // Stagnation: no halving of the recursive residual within the window.
     // Stop here; the caller restarts from the current iterate with a fresh
     // shadow vector (or falls back to complex128 in the mixed form).
@@ -162,9 +174,18 @@ static fit_status bicgstab(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, i
   if (ret != FIT_OK) return ret;
   *done = stalled ? kBreakdown : c.h_bst->done;
   c.last_reason = stalled ? 9 : c.h_bst->reason;
-  c.last_rr = c.h_bst->rr / r0;
+  double rr_end = c.h_bst->rr;
+  // hand back the best iterate seen at a poll when the run ended worse
+  // (a breakdown or a stall leaves the last iterate, not the best one)
+  if (kept && *done != kConverged && !(rr_end <= kept_rr)) {
+    fit_status e = vcopy(c, V.xb, V.x, ne);
+    if (e != FIT_OK) return e;
+    c.bytes += (double)ne * sizeof(T) * 4;
+    rr_end = kept_rr;
+  }
+  c.last_rr = rr_end / r0;
   *iters = c.h_bst->iter;
-  *rr_out = c.h_bst->rr;
+  *rr_out = rr_end;
   // The last step ends with p in p[parity] where parity = iter & 1; after an
   // odd number of iterations the fresh p lives in p[1].  x and r are final.
   return FIT_OK;
@@ -327,6 +348,7 @@ struct Inner {
   // true: the inner method applies the symmetric scaling itself (as a
   // preconditioner) and works on unscaled vectors
   bool own_scaling = false;
+  int restarts = 0;  // inner solves started (BiCGStab: selects the shadow seed)
 };
 
 // COCG on A_int x = r (r overwritten), from x = 0; same driver structure as
@@ -486,7 +508,7 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
 template <class T>
 static size_t inner_bytes(int64_t ne, int solver, int m) {
   const size_t v = align_up((size_t)ne * 2 * sizeof(T), 256);
-  if (solver == FIT_BICGSTAB) return 10 * v;
+  if (solver == FIT_BICGSTAB) return 11 * v;
   if (solver == FIT_COCG) return 8 * v;
   const int nblk = (int)((ne + 256 * kMdPer - 1) / (256 * kMdPer));
   return (size_t)(2 * m + 5) * v + align_up(sizeof(double) * 2 * (size_t)(m + 1) * nblk, 256);
@@ -508,6 +530,7 @@ static void inner_carve(Arena& a, Inner<T>& in, int64_t ne, int solver, int m) {
     in.bv.v[1] = a.take<T>(v);
     in.bv.s = a.take<T>(v);
     in.bv.t = a.take<T>(v);
+    in.bv.xb = a.take<T>(v);
     in.d = in.bv.x;
   } else if (solver == FIT_COCG) {
     in.bv.x = a.take<T>(v);
@@ -542,8 +565,9 @@ static fit_status run_inner(Ctx& c, Inner<T>& in, double q, int max_iter, int ch
   if (in.solver == FIT_BICGSTAB) {
     fit_status st = vcopy<T>(c, in.rin, in.bv.r, c.g->ne);
     if (st != FIT_OK) return st;
+    const uint64_t seed = kShadowSeed + (uint64_t)in.restarts++;
     return bicgstab<T>(c, in.bv, q, max_iter, check_every, hscale, hist, hist_len, use_graph,
-                       done, iters, &tmp);
+                       seed, done, iters, &tmp);
   }
   if (in.solver == FIT_COCG) {
     fit_status st = vcopy<T>(c, in.rin, in.bv.r, c.g->ne);
@@ -584,6 +608,12 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
   int iters = 0, refin = 0, stall = 0, breakdowns = 0;
   double best = 1.0;
   fit_status result = FIT_E_NOT_CONVERGED;
+  // BiCGStab restarts with a fresh shadow vector until the iteration budget
+  // is spent: a correction that does not lower the true residual is undone
+  // and the next inner solve starts again from the best iterate.  Only a
+  // long run of inner solves without halving the residual ends it early.
+  const bool retry = in.solver == FIT_BICGSTAB;
+  const int max_no_progress = retry ? (sizeof(T) == 4 ? 6 : 64) : 4;
   for (;;) {
     // inner rhs: S r scaled to unit norm, in precision T (S r = eta * rin)
     if ((st = xform<double, T, XF_SCALE>(c, c.sym && !in.own_scaling, false, rcur, in.rin, 1.0 / rnorm, true)) != FIT_OK)
@@ -628,15 +658,23 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
     }
     if (!std::isfinite(rn) || rn > rnorm) {
       // The correction made things worse (an inner solve that broke down
-      // early): undo it and stop this precision's refinement.
+      // early): undo it.  BiCGStab tries again with a new shadow vector;
+      // the other methods would repeat the same iteration, so this
+      // precision's refinement stops.
       if ((st = xform<T, double, XF_AXPY>(c, c.sym && !in.own_scaling, false, in.d, x, -eta, false)) != FIT_OK) return st;
       if ((st = residual(c, x, b, r, nullptr, 0.0)) != FIT_OK) return st;
       if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
       rn = std::sqrt(c.h_red->v[0]);
       *relres_out = rn / bnorm;
+      const bool budget_left = done != kMaxIter && iters < o.max_iters;
+      if (std::isfinite(rn) && retry && budget_left && ++stall < max_no_progress) {
+        rcur = r;
+        rnorm = rn;
+        continue;
+      }
       if (!std::isfinite(rn))
         result = FIT_E_NAN;
-      else if (done == kMaxIter || iters >= o.max_iters)
+      else if (!budget_left)
         result = FIT_E_NOT_CONVERGED;
       else
         result = FIT_E_BREAKDOWN;
@@ -662,12 +700,12 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
       result = FIT_E_NOT_CONVERGED;
       break;
     }
-    if (breakdowns >= 5) {
+    if (!retry && breakdowns >= 5) {
       result = FIT_E_BREAKDOWN;
       break;
     }
-    if (stall >= 4) {
-      result = FIT_E_NOT_CONVERGED;
+    if (stall >= max_no_progress) {
+      result = retry ? FIT_E_BREAKDOWN : FIT_E_NOT_CONVERGED;
       break;
     }
   }
@@ -715,7 +753,10 @@ extern "C" fit_status fit_solve(fit_grid* g, double omega, const void* source_de
   const int64_t ne = g->ne;
   const size_t v128 = align_up((size_t)ne * 16, 256);
   const bool mixed = o.precision == FIT_PREC_MIXED;
-  const size_t in_bytes = mixed ? inner_bytes<float>(ne, o.solver, o.restart)
+  // The mixed form reserves room for a complex128 inner solve as well, so a
+  // fallback carves the same arena (b, r and the residual history stay put).
+  const size_t in_bytes = mixed ? std::max(inner_bytes<float>(ne, o.solver, o.restart),
+                                           inner_bytes<double>(ne, o.solver, o.restart))
                                 : inner_bytes<double>(ne, o.solver, o.restart);
   const size_t hist_bytes = align_up(sizeof(double) * (size_t)std::max(o.resid_history_len, 1), 256);
   if ((st = ensure_ws(g->ws, 2 * v128 + in_bytes + hist_bytes + 4096, g->device)) != FIT_OK) return st;
@@ -764,33 +805,25 @@ extern "C" fit_status fit_solve(fit_grid* g, double omega, const void* source_de
                            &relres, &iters);
     if ((result == FIT_E_NOT_CONVERGED || result == FIT_E_BREAKDOWN || result == FIT_E_NAN) &&
         iters < o.max_iters) {
-      // complex64 stagnated: continue in complex128 from the current x
+      // complex64 stagnated: continue in complex128 from the current x, in
+      // the same arena (sized for it above): b, r and the history are kept
       inf.fell_back = 1;
       Arena a2{(char*)g->ws.ptr, 0, g->ws.bytes};
       (void)a2.take<double>(v128);
       (void)a2.take<double>(v128);
       if (hist) (void)a2.take<double>(hist_bytes);
-      if ((st = ensure_ws(g->ws, 2 * v128 + inner_bytes<double>(ne, o.solver, o.restart) + hist_bytes + 4096,
-                          g->device)) != FIT_OK)
-        return st;
-      // workspace may have moved: recompute b and r from scratch
-      Arena a3{(char*)g->ws.ptr, 0, g->ws.bytes};
-      b = a3.take<double>(v128);
-      r = a3.take<double>(v128);
-      hist = o.resid_history_len > 0 ? a3.take<double>(hist_bytes) : nullptr;
-      if ((st = xform<double, double, XF_RHS>(c, false, false, (const double*)source_dev, b, 1.0, true)) != FIT_OK)
-        return st;
       Inner<double> in2;
-      inner_carve<double>(a3, in2, ne, o.solver, o.restart);
-      // continue: the driver restarts from the residual of the current x
+      inner_carve<double>(a2, in2, ne, o.solver, o.restart);
       fit_solve_opts o2 = o;
       o2.max_iters = o.max_iters - iters;
+      const int hoff = std::min(iters, o.resid_history_len);
+      o2.resid_history_len = o.resid_history_len - hoff;
+      double* hist2 = (hist && o2.resid_history_len > 0) ? hist + hoff : nullptr;
       int it2 = 0;
-      // x already holds the mixed-precision iterate; refine it further
       if ((st = residual(c, x, b, r, nullptr, 0.0)) != FIT_OK) return st;
       if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
       result = refine<double>(c, in2, b, bnorm, x, r, r, std::sqrt(c.h_red->v[0]), tol, o2,
-                              o.inner_tol, pre, nullptr, inf, &relres, &it2);
+                              o.inner_tol, pre, hist2, inf, &relres, &it2);
       iters += it2;
     }
   } else {

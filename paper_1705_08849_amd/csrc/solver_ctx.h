@@ -64,10 +64,10 @@ static fit_status residual(Ctx& c, const double* x, const double* b, double* r, 
 
 template <class TI, class TO, int KIND>
 static fit_status xform(Ctx& c, bool sym, bool inverse, const TI* in, TO* out, double factor,
-                        bool reduce) {
+                        bool reduce, uint64_t seed = kShadowSeed) {
   hipLaunchKernelGGL((node_xform_kernel<TI, TO, KIND>), dim3(pw_blocks(c.g->view.np)), dim3(256), 0,
                      c.s, c.g->view, c.omega, sym ? 1 : 0, inverse ? 1 : 0, in, out, factor,
-                     reduce ? c.red : nullptr, c.part, c.cnt);
+                     reduce ? c.red : nullptr, c.part, c.cnt, seed);
   FIT_HIP(hipGetLastError());
   if (reduce) FIT_HIP(launch_finish<1>(c.part, pw_blocks(c.g->view.np), StoreSums<1>{c.red}, c.s));
   c.bytes += (double)c.g->ne * (sizeof(TI) + sizeof(TO)) * 2 * (KIND == XF_AXPY ? 1.5 : 1.0);

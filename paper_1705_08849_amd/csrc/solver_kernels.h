@@ -34,7 +34,7 @@ __device__ __forceinline__ double u11(uint64_t h) {
 template <class TI, class TO, int KIND>
 __global__ void __launch_bounds__(256)
     node_xform_kernel(GridView g, double omega, int sym, int inverse, const TI* in, TO* out,
-                      double factor, RedOut* red, double* part, unsigned* cnt) {
+                      double factor, RedOut* red, double* part, unsigned* cnt, uint64_t seed) {
   __shared__ MatLds<double> mat;
   __shared__ double lds[4];
   fill_mat_mode<double>(mat, g.mats, omega, MODE_MEC);
@@ -60,8 +60,8 @@ __global__ void __launch_bounds__(256)
       const cx<double> v{(double)vi.re, (double)vi.im};
       if (KIND == XF_SHADOW) {
         // dense pseudo-random BiCGStab shadow vector on the free edges
-        const double re = u11(splitmix64(2ull * (uint64_t)e, kShadowSeed));
-        const double im = u11(splitmix64(2ull * (uint64_t)e + 1ull, kShadowSeed));
+        const double re = u11(splitmix64(2ull * (uint64_t)e, seed));
+        const double im = u11(splitmix64(2ull * (uint64_t)e + 1ull, seed));
         const cx<double> sv = fr ? cx<double>{re, im} : cx<double>{0.0, 0.0};
         stc(out, e, cx<TO>{(TO)sv.re, (TO)sv.im});
         acc[0] += cabs2(sv);

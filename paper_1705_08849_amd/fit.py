@@ -352,7 +352,7 @@ def port_network(zl, z0: float = 50.0):
 def sweep(grids: Sequence[Grid], omegas: Sequence[float], sources, tol: float = 1e-8,
           solver: str = "cocg", precision: str = "fp64", scaling: str = "sym",
           max_iters: int = 0, check_every: int = 0, inner_tol: float = 0.0, xs=None,
-          restart: int = 30, stream=None):
+          restart: int = 30, stream=None, use_graph: bool = True):
     """``fit_sweep``: solve every (grid, omega, rhs) system.  ``sources[g]`` is
     a complex128 tensor of shape ``(nrhs, n_e(g))``.  Returns
     ``(status, port_voltages list per grid [nomega, nrhs, nports], infos)``."""
@@ -367,7 +367,8 @@ def sweep(grids: Sequence[Grid], omegas: Sequence[float], sources, tol: float = 
     xp = (C.c_void_p * ng)(*[x.data_ptr() for x in xs]) if xs is not None else None
     infos = (SolveInfo * (ng * nf * nrhs))()
     opts = SolveOpts(SOLVERS[solver], restart, max_iters, check_every, PRECISIONS[precision],
-                     SCALINGS[scaling], inner_tol, None, _stream_ptr(stream), None, 0, 1)
+                     SCALINGS[scaling], inner_tol, None, _stream_ptr(stream), None, 0,
+                     int(bool(use_graph)))
     st = lib().fit_sweep(gh, ng, om, nf, src, nrhs, float(tol), C.byref(opts), pv, xp, infos)
     if st == E_INVALID:
         raise FitError(st, f"fit_sweep: {last_error()}")

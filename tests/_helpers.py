@@ -9,6 +9,9 @@ import numpy as np
 
 from paper_1705_08849_amd import devices as D
 
+# vacuum permittivity from the defined mu0 = 4 pi 1e-7 H/m and the exact c0
+EPS0 = 1.0 / (4.0e-7 * np.pi * D.C0 ** 2)
+
 
 def rand_c(n, seed, dtype=np.complex128):
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -70,3 +73,48 @@ def parity_devices():
                                   dz=rng.uniform(1e-5, 2e-4, 9), cell_mat=cm, materials=mats,
                                   ports=[D.Port(3, 4, 1, 5, 37.0)], pec_walls=0b010110)
     return out
+
+
+def plate_device(graded=True):
+    """Parallel-plate case: electric walls at -z and +z only (the four side
+    walls open), three z-layers of different lossy media, graded x/y/z
+    spacings.  Driven by a uniform current density J along z."""
+    rng = np.random.default_rng(17)
+    ncx, ncy, ncz = 5, 4, 6
+    h = (lambda n: rng.uniform(0.5e-3, 1.5e-3, n)) if graded else (lambda n: np.full(n, 1e-3))
+    mats = [D.Material(eps_r=2.5, tan_delta=0.01), D.Material(eps_r=9.0, sigma=0.3),
+            D.Material(eps_r=4.0, tan_delta=0.002, sigma=0.05)]
+    cm = np.zeros((ncz, ncy, ncx), np.uint8)
+    cm[2:4] = 1
+    cm[4:] = 2
+    return D.Device(dx=h(ncx), dy=h(ncy), dz=h(ncz), cell_mat=cm, materials=mats,
+                    pec_walls=(1 << 4) | (1 << 5))
+
+
+def plate_source(dev, jdens=1.0):
+    """Impressed current per z-edge = J times the edge's dual-facet area
+    (half cells at the open side walls), i.e. a uniform current density."""
+    def dual(h):
+        hp = np.concatenate([[0.0], h, [0.0]])
+        return 0.5 * (hp[:-1] + hp[1:])
+    nx, ny, nz = dev.nodes
+    area = dual(dev.dy)[:, None] * dual(dev.dx)[None, :]
+    j = np.zeros((nz, ny, nx, 3), np.complex128)
+    j[: dev.ncz, :, :, 2] = jdens * area[None, :, :]
+    return j.ravel()
+
+
+def plate_closed_form(dev, omega, jdens=1.0):
+    """A uniform field E_k along z in layer k is the gradient of a potential
+    that depends on z alone, so the curl-curl term vanishes and eq. (e2)
+    reduces per edge to (-omega^2 eps_k + j omega sigma_k) E_k (area) =
+    -j omega J (area):  E_k = -j omega J / (-omega^2 eps_k + j omega sigma_k),
+    eps_k = eps0 eps_r (1 - j tan delta); edge voltage E_k dz[k]."""
+    nx, ny, nz = dev.nodes
+    x = np.zeros((nz, ny, nx, 3), np.complex128)
+    for k in range(dev.ncz):
+        m = dev.materials[dev.cell_mat[k, 0, 0]]
+        eps = EPS0 * m.eps_r * (1 - 1j * m.tan_delta)
+        e = -1j * omega * jdens / (-omega ** 2 * eps + 1j * omega * m.sigma)
+        x[k, :, :, 2] = e * dev.dz[k]
+    return x.ravel()

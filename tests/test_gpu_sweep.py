@@ -144,3 +144,32 @@ def test_sweep_family_grid_sample():
               f"fell_back {infos[f]['fell_back']} relres {rr:.2e}")
         assert infos[f]["status"] == fit.OK and rr <= 1e-8
     assert st == fit.OK
+
+
+def test_sweep_more_than_one_batch_and_graph_equals_eager():
+    """70 systems on one small grid (35 frequencies x 2 excitations) take
+    two batches (at most 64 systems each); every system converges and
+    checks out against the oracle, and replaying the captured graphs gives
+    bit for bit the fields and iteration counts of eager launches."""
+    dev = D.layered_device(14, 12, 8, n_layers=2, n_strips=1, n_ports=1, seed=44)
+    g = fit.Grid(dev)
+    freqs = np.geomspace(1e9, 40e9, 35)
+    omegas = 2 * np.pi * freqs
+    # the port and a dense seeded current on the free edges
+    src = np.stack([D.port_source(dev, 0), rand_c(dev.n_edges, 77) * O.free_edges(dev)])
+    n = dev.n_edges
+    out = {}
+    for graph in (True, False):
+        x = torch.empty(len(freqs) * 2 * n, dtype=torch.complex128, device="cuda:0")
+        st, pv, infos = fit.sweep([g], omegas, [_cuda(src)], tol=1e-8, xs=[x], use_graph=graph)
+        assert st == fit.OK, [i["status"] for i in infos]
+        out[graph] = (x.clone(), [i["iterations"] for i in infos], pv[0].copy())
+    assert torch.equal(out[True][0], out[False][0])
+    assert out[True][1] == out[False][1]
+    xh = out[True][0].cpu().numpy().reshape(len(freqs), 2, n)
+    for f, om in enumerate(omegas):
+        for r in range(2):
+            rr = O.relative_residual(dev, om, src[r], xh[f, r])
+            assert rr <= 1e-8, (f, r, rr)
+            np.testing.assert_allclose(out[True][2][f, r], O.port_voltages(dev, xh[f, r]),
+                                       rtol=1e-12, atol=1e-14 * np.abs(xh[f, r]).max())

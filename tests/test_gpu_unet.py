@@ -156,14 +156,19 @@ def test_fgmres_with_the_network_tracks_the_oracle():
     assert abs(r_plain - rc) > 0.1 * rc
 
 
-def test_full_size_family_device_properties():
+@pytest.mark.timeout(600)
+def test_full_size_family_device():
     """The 192x192x96-cell family device at full size, the application the
-    benchmark times (c = 16): the output is finite, zero on masked edges,
-    and exactly equivariant to a power-of-two scaling of the input (z = s
-    U(v / s) with s the rms of v, so v -> 2 v gives z -> 2 z bit for bit)."""
+    benchmark times (c = 16): element by element against the oracle's FP64
+    forward pass over the whole padded grid (the same bf16 storage
+    roundings), and exactly equivariant to a power-of-two scaling of the
+    input (z = s U(v / s) with s the rms of v, so v -> 2 v gives z -> 2 z
+    bit for bit)."""
     dev = D.learned_family_device(9000)
     g = fit.Grid(dev)
-    pre = fit.Precond.create(base_channels=16, seed=1)
+    c = 16
+    p = U.init_params(c, seed=1).astype(np.float32).astype(np.float64)
+    pre = fit.Precond.load(fit.Precond.blob_from_params(c, p))
     free = O.free_edges(dev)
     v = rand_c(dev.n_edges, 41) * free
     om = 2 * np.pi * 1e10
@@ -174,3 +179,8 @@ def test_full_size_family_device_properties():
     assert np.all(z1[~free] == 0)
     assert np.linalg.norm(z1) > 0
     np.testing.assert_array_equal(z2, 2 * z1)
+    zr = U.apply(dev, om, p, v, free, c=c, bf16=True)
+    rel = np.linalg.norm(z1 - zr) / np.linalg.norm(zr)
+    print(f"192x192x96 c=16 application vs oracle: rel err {rel:.3e}")
+    # the small-grid bar: fp32 accumulation order can flip a stored bf16 value
+    assert rel <= 1e-2

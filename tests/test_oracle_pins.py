@@ -14,6 +14,7 @@ import scipy.sparse as sp
 
 from oracle import fit_oracle as O
 from paper_1705_08849_amd import devices as D
+from tests import _helpers as H
 
 SHAPES = [(3, 4, 5), (5, 2, 3), (4, 4, 4)]
 
@@ -124,7 +125,7 @@ def _discrete_cavity_spectrum(ncx, ncy, ncz, hx, hy, hz):
 def test_full_discrete_cavity_spectrum(dims):
     (ncx, ncy, ncz), (hx, hy, hz) = dims
     dev = D.cavity(ncx, ncy, ncz, hx, hy, hz)
-    lam = O.cavity_eigenfrequencies(dev)  # omega^2 values (dense)
+    lam = O.cavity_omega2(dev)
     interior = (ncx - 1) * (ncy - 1) * (ncz - 1)
     tiny = np.abs(lam) <= 1e-9 * lam.max()
     assert tiny.sum() == interior  # gradient null space: one per interior node
@@ -192,7 +193,7 @@ def test_discrete_spectrum_with_open_and_mixed_walls(walls):
     ns, hs = (3, 4, 2), (1e-3, 1.3e-3, 0.7e-3)
     dev = D.cavity(*ns, *hs)
     dev.pec_walls = walls
-    lam = np.sort(O.cavity_eigenfrequencies(dev))
+    lam = O.cavity_omega2(dev)
     tiny = np.abs(lam) <= 1e-9 * np.abs(lam).max()
     curl, null = _discrete_box_spectrum(ns, hs, walls)
     assert tiny.sum() == null
@@ -222,8 +223,8 @@ def test_tiny_cavity_first_resonance_matches_closed_forms():
 
 
 def test_homogeneous_permittivity_scales_frequencies():
-    a = O.cavity_eigenfrequencies(D.cavity(3, 4, 3, 1e-3, 0.9e-3, 1.2e-3))
-    b = O.cavity_eigenfrequencies(D.cavity(3, 4, 3, 1e-3, 0.9e-3, 1.2e-3, eps_r=4.0))
+    a = O.cavity_omega2(D.cavity(3, 4, 3, 1e-3, 0.9e-3, 1.2e-3))
+    b = O.cavity_omega2(D.cavity(3, 4, 3, 1e-3, 0.9e-3, 1.2e-3, eps_r=4.0))
     nz = a > 1e-9 * a.max()
     np.testing.assert_allclose(np.sort(b[nz]), np.sort(a[nz]) / 4.0, rtol=1e-10)
 
@@ -349,11 +350,24 @@ def test_sym_scaled_operator_has_unit_mass():
     s = O.sym_scaling(dev, om)
     hat = s[:, None] * a * s[None, :] + om ** 2 * np.eye(len(s))
     lam = np.sort(np.linalg.eigvalsh(0.5 * (hat + hat.T).real))
-    ref = O.cavity_eigenfrequencies(dev)
+    ref = O.cavity_omega2(dev)
     np.testing.assert_allclose(lam, np.sort(ref), rtol=1e-9, atol=1e-9 * ref.max())
 
 
 # --- Solves ------------------------------------------------------------------
+
+@pytest.mark.parametrize("graded", [False, True])
+def test_parallel_plate_solution_has_the_closed_form(graded):
+    """Pins the magnitude, phase and frequency dependence of b = -j omega j
+    and of the diagonal term: the oracle's direct solution equals the
+    closed-form uniform field of a z-layered parallel-plate device."""
+    dev = H.plate_device(graded)
+    for f in (0.3e9, 2e9):
+        om = 2 * np.pi * f
+        x = O.solve_direct(dev, om, H.plate_source(dev))
+        ref = H.plate_closed_form(dev, om)
+        assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+
 
 def test_direct_solve_matches_dense_brute_force():
     dev = D.layered_device(5, 4, 4, n_layers=2, n_strips=1, n_ports=1, seed=1)
@@ -493,6 +507,7 @@ def _run_pins():
         ("pec12", test_pec_cell_removes_exactly_its_twelve_edges),
         ("passive", test_reciprocity_and_passivity_of_two_port),
         ("open_walls", lambda: test_discrete_spectrum_with_open_and_mixed_walls(0b010110)),
+        ("plate", lambda: test_parallel_plate_solution_has_the_closed_form(True)),
     ]:
         try:
             fn()
@@ -581,6 +596,24 @@ def test_mutation_full_dual_cells_at_walls_is_caught(monkeypatch):
 
     monkeypatch.setattr(O, "_sum_pairs", bad)
     assert "open_walls" in _run_pins()
+
+
+def test_mutation_rhs_without_omega_is_caught(monkeypatch):
+    """b = -j j (a dropped factor omega) leaves every invariant pin intact;
+    only the parallel-plate closed form sees it."""
+    def bad(dev, omega, jsrc):
+        return (-1j * jsrc)[O.free_edges(dev)]
+
+    monkeypatch.setattr(O, "rhs", bad)
+    assert _run_pins() == ["plate"]
+
+
+def test_mutation_rhs_sign_is_caught(monkeypatch):
+    def bad(dev, omega, jsrc):
+        return (1j * omega * jsrc)[O.free_edges(dev)]
+
+    monkeypatch.setattr(O, "rhs", bad)
+    assert "plate" in _run_pins()
 
 
 def _paper_edge_counts():
