@@ -250,6 +250,18 @@ fit_status fit_sweep(struct fit_grid *const *grids, int ngrids, const double *om
 fit_status fit_port_voltages(const struct fit_grid *g, const void *x_dev, int nvec,
                              double *out_host, void *stream);
 
+/* fit_port_voltages for callers that cannot allocate device memory (code
+ * inside a tight serving loop, or a harness that forbids hipMalloc): the same
+ * kernel and the same result, bit for bit, but the port sums are staged in a
+ * static device array of 65536 complex128 values (1 MiB) that every GPU the
+ * library runs on keeps until the process ends, instead of a buffer
+ * allocated per call.  Calls no allocating routine.  FIT_E_INVALID (nothing
+ * written) for the bad arguments of fit_port_voltages and for
+ * nvec * nports > 65536.  Calls that overlap on one GPU share the array and
+ * race: serialise them (one stream, or host-side ordering).  Synchronous. */
+fit_status fit_port_voltages_noalloc(const struct fit_grid *g, const void *x_dev, int nvec,
+                                     double *out_host, void *stream);
+
 /* Network parameters of the ports (Sec. IV port model: each lumped port is a
  * 1 A source in parallel with its internal impedance z0, which the port's
  * edges carry as conductance).  Host-only and synchronous.

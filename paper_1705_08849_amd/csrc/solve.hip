@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "fit_internal.h"
@@ -920,4 +921,64 @@ extern "C" fit_status fit_port_voltages(const fit_grid* g, const void* x_dev, in
   }
   (void)hipFree(d);
   return st;
+}
+
+// ---------------------------------------------------------------------------
+// Port voltages without any allocation: the per-call device buffer of
+// fit_port_voltages is replaced by a file-scope device array.  Every GPU the
+// library runs on holds its own copy of the array until the process ends; its
+// address on a device is looked up once, with that device current, and kept.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kPortScratchValues = 65536;  // complex128 port sums per call (1 MiB)
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) double scratch[2 * kPortScratchValues];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The device address of `scratch` on `device` (which must be current).
+fit_status scratch_for(int device, double** out) {
+  if (device < 0 || device >= kMaxScratchDevices) {
+    set_error("fit_port_voltages_noalloc: device ordinal outside the supported range");
+    return FIT_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return FIT_OK;
+}
+}  // namespace
+
+extern "C" fit_status fit_port_voltages_noalloc(const fit_grid* g, const void* x_dev, int nvec,
+                                                double* out_host, void* stream) {
+  if (!g || !x_dev || !out_host || nvec < 1) {
+    set_error("fit_port_voltages_noalloc: bad argument");
+    return FIT_E_INVALID;
+  }
+  if (g->nports == 0) return FIT_OK;
+  if ((int64_t)nvec * g->nports > kPortScratchValues) {
+    set_error("fit_port_voltages_noalloc: nvec * nports exceeds the 65536 values of the static "
+              "scratch array");
+    return FIT_E_INVALID;
+  }
+  DeviceScope dev(g->device);
+  double* d = nullptr;
+  fit_status st = scratch_for(g->device, &d);
+  if (st != FIT_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // port_sum_kernel writes every one of the nvec * nports values, so nothing
+  // left from an earlier call can reach the output
+  st = port_voltages_dev(g, x_dev, nvec, d, s);
+  if (st != FIT_OK) return st;
+  const size_t bytes = sizeof(double) * 2 * (size_t)nvec * g->nports;
+  hipError_t e = hipMemcpyAsync(out_host, d, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "port voltages copy");
+  return FIT_OK;
 }

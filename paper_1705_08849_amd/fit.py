@@ -123,6 +123,8 @@ _SIGS = [
                             C.POINTER(C.c_double), C.POINTER(C.c_void_p), C.POINTER(SolveInfo)]),
     ("fit_port_voltages", C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_double),
                                     C.c_void_p]),
+    ("fit_port_voltages_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_int,
+                                            C.POINTER(C.c_double), C.c_void_p]),
     ("fit_port_network", C.c_int, [C.c_int, C.c_double, C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("fit_precond_train", C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_double),
@@ -323,11 +325,14 @@ class Grid:
             raise FitError(st, f"fit_solve: {last_error()} (info={d})")
         return x, d
 
-    def port_voltages(self, x, nvec: int = 1, stream=None) -> np.ndarray:
+    def port_voltages(self, x, nvec: int = 1, stream=None, noalloc: bool = False) -> np.ndarray:
+        """Port sums of ``nvec`` fields stored back to back; ``noalloc`` calls
+        ``fit_port_voltages_noalloc`` (static device scratch, no allocation)."""
         n = len(self.dev.ports)
         out = (C.c_double * (2 * max(1, n * nvec)))()
-        check(lib().fit_port_voltages(self.h, _dptr(x), nvec, out, _stream_ptr(stream)),
-              "fit_port_voltages")
+        fn = lib().fit_port_voltages_noalloc if noalloc else lib().fit_port_voltages
+        check(fn(self.h, _dptr(x), nvec, out, _stream_ptr(stream)),
+              "fit_port_voltages_noalloc" if noalloc else "fit_port_voltages")
         a = np.frombuffer(out, dtype=np.float64)[: 2 * n * nvec].copy()
         return a.view(np.complex128).reshape(nvec, n)
 
