@@ -193,26 +193,45 @@ def sweep_row(fit, D, np, torch, with_cpu):
            "sequential_points_per_s": round(16 / ts, 3), "speedup": round(ts / tb, 3),
            "iterations": [min(iters), max(iters)]}
     if with_cpu:
-        import scipy.sparse as sp
-        from threadpoolctl import threadpool_limits
-
-        from oracle import fit_oracle as O
-        om = float(oms[8])
-        with threadpool_limits(1):
-            t0 = time.perf_counter()
-            a = O.system_matrix(sd, om)
-            s = O.sym_scaling(sd, om)
-            as_ = (sp.diags(s) @ a @ sp.diags(s)).tocsr()
-            b = s * O.rhs(sd, om, D.port_source(sd, 0))
-            t1 = time.perf_counter()
-            O.cocg(as_, b, tol=1e-30, maxiter=20)
-            t2 = time.perf_counter()
-        per_point = (t1 - t0) + (t2 - t1) / 20 * float(np.mean(iters))
-        row["cpu_baseline"] = {"value": round(1.0 / per_point, 5), "unit": "freq-points/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": "assembly + 20 COCG iterations at the middle frequency on one "
-                                         "host thread, extrapolated with the GPU's mean iteration count"}
+        import multiprocessing as mp
+        workers = max(1, min(16, os.cpu_count() or 1, len(oms)))
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(workers) as pool:
+            per = pool.map(_sweep_cpu_point, [(float(om), it) for om, it in zip(oms, iters)])
+        wall = time.perf_counter() - t0
+        # every worker ran one frequency's sample concurrently (memory
+        # bandwidth shared as in a full run); each sample is extrapolated to
+        # its GPU iteration count and the points are spread over the workers
+        est = sum(per) / workers
+        row["cpu_baseline"] = {"value": round(len(oms) / est, 5), "unit": "freq-points/s",
+                               "cores": workers, "kind": "oracle",
+                               "sample": f"{len(oms)} frequencies on a pool of {workers} single-thread "
+                                         "workers, each: assembly + 20 COCG iterations, extrapolated "
+                                         "with that point's GPU iteration count; points spread over "
+                                         f"the workers (sample wall {wall:.1f} s)"}
     return row
+
+
+def _sweep_cpu_point(arg):
+    """One sweep point of the oracle in a pool worker (one thread):
+    assembly and scaling, 20 COCG iterations, extrapolated to `iters`."""
+    om, iters = arg
+    from threadpoolctl import threadpool_limits
+    import scipy.sparse as sp
+
+    from oracle import fit_oracle as O
+    from paper_1705_08849_amd import devices as D
+    sd = D.sweep_devices(seeds=[40], shapes=[(64, 64, 32)])[0]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        a = O.system_matrix(sd, om)
+        s = O.sym_scaling(sd, om)
+        as_ = (sp.diags(s) @ a @ sp.diags(s)).tocsr()
+        b = s * O.rhs(sd, om, D.port_source(sd, 0))
+        t1 = time.perf_counter()
+        O.cocg(as_, b, tol=1e-30, maxiter=20)
+        t2 = time.perf_counter()
+    return (t1 - t0) + (t2 - t1) / 20 * iters
 
 
 def precond_row(fit, D, np, torch, with_cpu):
@@ -274,6 +293,81 @@ def precond_row(fit, D, np, torch, with_cpu):
     return row
 
 
+def interconnect_row(fit, D, np, torch, mean_us):
+    """The 256x256x128-cell interconnect (25.6M unknowns, 835 MB per complex128
+    operator application, beyond the 256 MB last-level cache): the plain
+    operator's bandwidth and the copy bandwidth on vectors of its size, one
+    COCG complex128 solve at 10 GHz, and the fused COCG step's HIP-event
+    time per launch during that solve."""
+    dev = D.interconnect_256(3)
+    nx, ny, nz = dev.nodes
+    n_nodes, n_cells = nx * ny * nz, dev.ncx * dev.ncy * dev.ncz
+    om = 2 * np.pi * 10e9
+    g = fit.Grid(dev)
+    xv = torch.randn(dev.n_edges, dtype=torch.complex128, device="cuda:0")
+    yv = torch.empty_like(xv)
+    mv_us = mean_us(lambda: g.matvec(om, xv, yv, scaling="none"))
+    mv_bytes = n_nodes * 6 * 16 + n_cells
+    cp_us = mean_us(lambda: yv.copy_(xv))
+    copy_gbs = 2 * xv.numel() * 16 / cp_us / 1e3
+    x32 = xv.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    mv32_us = mean_us(lambda: g.matvec(om, x32, y32, scaling="none"))
+    mv32_bytes = n_nodes * 6 * 8 + n_cells
+    del xv, yv, x32, y32
+    src = torch.from_numpy(D.port_source(dev, 0)).to("cuda:0")
+    torch.cuda.synchronize()
+    fit.profile_start()
+    t0 = time.perf_counter()
+    x, info = g.solve(om, src, tol=1e-8, solver="cocg", raise_on_error=False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    stats = fit.profile_stop()
+    launches, total_ms = stats.get("pcocg_step1_c128", (0, 0.0))
+    step_us = total_ms * 1e3 / launches if launches else None
+    step_bytes = n_nodes * 3 * 16 * 6 + n_cells
+    row = {"workload": "256x256x128-cell graded interconnect (seed 3, 8 layers, 12 PEC strips, one "
+                       "50-Ohm port), 10 GHz, COCG complex128 to 1e-8, symmetric scaling",
+           "unknowns": dev.n_edges,
+           "status": info["status_name"], "iterations": info["iterations"],
+           "true_relres": info["true_relres"], "solve_s": round(ts, 2),
+           "points_per_s": round((1.0 if info["status_name"] == "FIT_OK" else 0.0) / ts, 5),
+           "matvec": {"kernel": "matvec A(omega) c128", "us": round(mv_us, 2),
+                      "achieved": round(mv_bytes / mv_us / 1e3, 1), "unit": "GB/s",
+                      "frac": round(mv_bytes / mv_us / 1e3 / HBM_PEAK_GBS, 4), "alg_bytes": mv_bytes,
+                      "copy_gbs": round(copy_gbs, 1),
+                      "frac_of_copy": round(mv_bytes / mv_us / 1e3 / copy_gbs, 4),
+                      "timing": "mean of 20 back-to-back launches, HIP events"},
+           "matvec_c64": {"us": round(mv32_us, 2), "achieved": round(mv32_bytes / mv32_us / 1e3, 1),
+                          "unit": "GB/s", "frac": round(mv32_bytes / mv32_us / 1e3 / HBM_PEAK_GBS, 4),
+                          "alg_bytes": mv32_bytes}}
+    if step_us:
+        row["pcocg_step1_c128"] = {"avg_launch_us": round(step_us, 2), "launches": launches,
+                                   "alg_bytes_per_launch": step_bytes,
+                                   "achieved": round(step_bytes / step_us / 1e3, 1), "unit": "GB/s",
+                                   "frac": round(step_bytes / step_us / 1e3 / HBM_PEAK_GBS, 4)}
+    del x, src, g
+    torch.cuda.empty_cache()
+    return row
+
+
+def mean_us(fn, reps=20):
+    """Mean launch time over `reps` back-to-back launches between two HIP
+    events on torch's current stream, which the launches use (events around
+    each launch would add the event overhead)."""
+    import torch
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1000 / reps
+
+
 def cpu_baseline(dev, omega, src, gpu_iters):
     """The FP64 oracle as it stands, one thread: assemble and scale the
     system, time 30 COCG iterations (about 10 s of CPU work in all),
@@ -324,7 +418,7 @@ def main():
                     help="with --autotune: write the tile table to the committed file")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the secondary rows (batched sweep, learned preconditioner)")
-    ap.add_argument("--row", choices=["sweep", "precond"],
+    ap.add_argument("--row", choices=["sweep", "precond", "interconnect"],
                     help="run only this secondary row and print it as one JSON line")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short sample profiled by the HBM-counter passes")
@@ -353,8 +447,12 @@ def main():
         from paper_1705_08849_amd import fit
 
         torch.cuda.init()
-        fn = {"sweep": sweep_row, "precond": precond_row}[args.row]
-        print(json.dumps({"row": args.row, **fn(fit, D, np, torch, not args.no_cpu_baseline)}), flush=True)
+        if args.row == "interconnect":
+            row = interconnect_row(fit, D, np, torch, mean_us)
+        else:
+            fn = {"sweep": sweep_row, "precond": precond_row}[args.row]
+            row = fn(fit, D, np, torch, not args.no_cpu_baseline)
+        print(json.dumps({"row": args.row, **row}), flush=True)
         return
 
     import numpy as np
@@ -382,24 +480,11 @@ def main():
     # plain operator bandwidth (the metric's second part)
     xv = torch.randn(dev.n_edges, dtype=torch.complex128, device="cuda:0")
     yv = torch.empty_like(xv)
-    def mean_us(fn, reps=20):
-        """Mean launch time over `reps` back-to-back launches between two HIP
-        events (events around each launch would add the event overhead)."""
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) * 1000 / reps
-
     mv_us = mean_us(lambda: g.matvec(omega, xv, yv, scaling="none"))
     mv_bytes = n_nodes * 6 * 16 + n_cells
     # this device's copy bandwidth on vectors of the same size, as a
-    # second reference besides the 8 TB/s peak
+    # second reference besides the 8 TB/s peak (two 103 MB vectors fit the
+    # 256 MB last-level cache: the HBM figures come from the interconnect row)
     cp_us = mean_us(lambda: yv.copy_(xv))
     copy_gbs = 2 * xv.numel() * 16 / cp_us / 1e3
     del xv, yv
@@ -407,7 +492,7 @@ def main():
     def step():
         xs, info = g.solve(omega, src, tol=1e-8, solver=args.solver, precision=args.precision,
                            x=x, raise_on_error=False)
-        u = g.port_voltages(xs)
+        u = g.port_voltages(xs, noalloc=True)  # no allocation inside the timed region
         return info, u
 
     for _ in range(args.warmup):
@@ -484,10 +569,17 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dev, omega, src_np, iters)
+    # the plain operator's bandwidth on the largest single-GPU grid (its
+    # working set exceeds the last-level cache), with the fused COCG step and
+    # one solve there
+    del g, x
+    torch.cuda.empty_cache()
+    ic = interconnect_row(fit, D, np, torch, mean_us)
+    out["matvec_128"] = out["matvec"]
+    out["matvec"] = dict(ic["matvec"], grid="256x256x128 cells (835 MB per application)")
     if not args.no_rows:
-        del g
-        torch.cuda.empty_cache()
-        out["rows"] = {"sweep": sweep_row(fit, D, np, torch, not args.no_cpu_baseline),
+        out["rows"] = {"interconnect": ic,
+                       "sweep": sweep_row(fit, D, np, torch, not args.no_cpu_baseline),
                        "precond": precond_row(fit, D, np, torch, not args.no_cpu_baseline)}
     print(json.dumps(out), flush=True)
 

@@ -63,20 +63,54 @@ typedef enum { FIT_C128 = 0, FIT_C64 = 1 } fit_dtype;
 /* FIT_SCALE_NONE: y = A(omega) x, the operator of eq. (e2) with losses.
  * FIT_SCALE_SYM:  y = S A(omega) S x with S = diag(M_eps,c^{-1/2}),
  *   M_eps,c = M_eps - j M_sigma / omega: the symmetrically scaled operator of
- *   eqs. (e2s)/(e2t), S C^T M_nu C S - omega^2 I.  Requires omega > 0. */
-typedef enum { FIT_SCALE_NONE = 0, FIT_SCALE_SYM = 1 } fit_scaling;
+ *   eqs. (e2s)/(e2t), S C^T M_nu C S - omega^2 I.  Requires omega > 0.
+ * FIT_SCALE_FACT: the same scaled operator in the factorized order of
+ *   eq. (e2tt), y = calA^T (calA x) - omega^2 x with
+ *   calA = M_mu^{-1/2} C S (the reluctance split as sqrt(M_nu) on both
+ *   factors).  fit_matvec only (fit_matvec_batched, fit_solve and fit_sweep
+ *   take NONE or SYM).  Requires omega > 0. */
+typedef enum { FIT_SCALE_NONE = 0, FIT_SCALE_SYM = 1, FIT_SCALE_FACT = 2 } fit_scaling;
 
 /* FIT_COCG is the paper's conjugate-gradient method (Sec. IV, "cg") in the
  * form that is valid for the complex symmetric (A = A^T, not Hermitian)
  * operator: CG recurrences with the unconjugated bilinear form x^T y
- * (conjugate orthogonal CG).  One operator application per iteration. */
-typedef enum { FIT_BICGSTAB = 0, FIT_GMRES = 1, FIT_FGMRES = 2, FIT_COCG = 3 } fit_solver;
+ * (conjugate orthogonal CG).  One operator application per iteration.
+ * FIT_COCR is the paper's conjugate residual method (Sec. IV, "cr") in the
+ * same complex symmetric form (CR recurrences with x^T y), one operator
+ * application per iteration; FIT_TFQMR is the transpose-free QMR method of
+ * the same comparison (Freund), two operator applications per iteration,
+ * stopping on its residual bound tau sqrt(m + 1) before the true residual is
+ * checked.  Both run on the internal operator (S A S with FIT_SCALE_SYM). */
+typedef enum {
+  FIT_BICGSTAB = 0,
+  FIT_GMRES = 1,
+  FIT_FGMRES = 2,
+  FIT_COCG = 3,
+  FIT_COCR = 4,
+  FIT_TFQMR = 5
+} fit_solver;
 
 /* FIT_PREC_FP64:  complex128 operator and Krylov vectors throughout.
  * FIT_PREC_MIXED: complex64 operator and inner Krylov iterations, complex128
  *   outer residual r = b - A x, solution update and stopping test
  *   (iterative refinement). */
 typedef enum { FIT_PREC_FP64 = 0, FIT_PREC_MIXED = 1 } fit_precision;
+
+/* Diagonal preconditioner of FIT_COCG, m = diag(M)^{-1} applied as z = m .* r
+ * (a complex symmetric diagonal, so COCG stays valid).
+ * FIT_DIAG_AUTO:   the symmetric scaling of eq. (e2t) when scaling is
+ *   FIT_SCALE_SYM (m = 1/M_eps,c recomputed inside the fused operator and
+ *   update kernels, nothing stored), none with FIT_SCALE_NONE.
+ * FIT_DIAG_MASS:   the same m = 1/M_eps,c, kept as a stored vector (unfused;
+ *   the same iterates up to rounding).
+ * FIT_DIAG_PAPER:  the paper's diagonal preconditioner of the factorized form
+ *   (Sec. III, eq. (Precond)): the squared column norms of
+ *   calA = M_mu^{-1/2} C M_eps^{-1/2}, P_ee = K_ee / M_eps,e with
+ *   K = C^T M_nu C; on the unscaled system this is m = 1/K_ee.
+ * FIT_DIAG_JACOBI: m = 1/diag(A(omega)) = 1/(K_ee + d_e).
+ * The stored forms cost one more vector and three more passes per iteration
+ * than FIT_DIAG_AUTO. */
+typedef enum { FIT_DIAG_AUTO = 0, FIT_DIAG_MASS = 1, FIT_DIAG_PAPER = 2, FIT_DIAG_JACOBI = 3 } fit_diag;
 
 /* One material (Sec. II, eq. (Material); complex permittivity for dielectric
  * losses eps0 eps_r (1 - j tan_delta); conductivity sigma [S/m]). */
@@ -135,6 +169,10 @@ typedef struct {
   int32_t resid_history_len;
   int32_t use_graph;   /* nonzero: replay captured hipGraphs of check_every
                           iterations instead of eager launches */
+  int32_t diag;        /* fit_diag: FIT_COCG's diagonal preconditioner; any value
+                          but FIT_DIAG_AUTO with another solver is
+                          FIT_E_UNSUPPORTED (fit_sweep ignores it) */
+  int32_t reserved;
 } fit_solve_opts;
 
 typedef struct {
@@ -174,6 +212,10 @@ fit_status fit_edge_mask(const struct fit_grid *g, uint8_t *mask_dev, void *stre
  *   kind 1: M_sigma per edge including port conductances (real part only)
  *   kind 2: M_nu = M_mu^{-1} per primal facet (facet (w,i,j,k) at the edge
  *           index formula), real part only
+ *   kind 3: the curl-curl diagonal K_ee = sum of M_nu over the four facets
+ *           that contain edge e (real part only), from which the paper's
+ *           diagonal preconditioner follows (Sec. III, eq. (Precond):
+ *           P_ee = K_ee / M_eps,e)
  * Written as complex128 into out_dev (n_e elements), for every index
  * including masked and ghost ones.  Asynchronous on `stream`. */
 fit_status fit_material_diag(const struct fit_grid *g, int kind, double *out_dev, void *stream);

@@ -257,13 +257,39 @@ def sym_scaling(dev, omega: float) -> np.ndarray:
     return 1.0 / np.sqrt((m_eps - 1j * m_sig / omega)[f])
 
 
+def scaled_curl(dev, omega: float) -> sp.csr_matrix:
+    """``calA = M_mu^{-1/2} C M_eps,c^{-1/2}`` of Sec. III (the factor before
+    eq. (e2tt)): rows are primal facets, columns the free edges; the
+    reluctance enters as its square root, the permittivity as the symmetric
+    scaling of :func:`sym_scaling`."""
+    nx, ny, nz = dev.nodes
+    f = free_edges(dev)
+    c = curl(nx, ny, nz).astype(np.float64).tocsc()[:, f]
+    return (sp.diags(np.sqrt(facet_reluctance(dev))) @ c @ sp.diags(sym_scaling(dev, omega))).tocsr()
+
+
+def paper_diag_preconditioner(dev, omega: float) -> np.ndarray:
+    """Eq. (Precond): ``P_ii = sum_k [calA]_ki^2``, the column sums of the
+    squared (unconjugated) entries of ``calA``, on the free edges.  The
+    preconditioner of the scaled system is ``1/P``."""
+    a = scaled_curl(dev, omega)
+    return np.asarray(a.multiply(a).sum(axis=0)).ravel()
+
+
 def matvec(dev, omega: float, x: np.ndarray, scaling: str = "none") -> np.ndarray:
     """``y = A(omega) x`` on all edges: free-edge rows of the assembled
     matrix applied to the free-edge part of ``x``; ``y`` is zero elsewhere.
-    ``scaling='sym'`` applies ``S A S`` instead (eq. (e2t))."""
+    ``scaling='sym'`` applies ``S A S`` instead (eq. (e2t)); ``scaling='fact'``
+    applies the factorized form of eq. (e2tt), ``calA^T (calA x) - omega^2 x``."""
     f = free_edges(dev)
-    a = system_matrix(dev, omega)
     xf = np.asarray(x, np.complex128)[f]
+    if scaling == "fact":
+        a = scaled_curl(dev, omega)
+        yf = a.T @ (a @ xf) - omega * omega * xf
+        y = np.zeros(dev.n_edges, np.complex128)
+        y[f] = yf
+        return y
+    a = system_matrix(dev, omega)
     if scaling == "sym":
         s = sym_scaling(dev, omega)
         yf = s * (a @ (s * xf))
@@ -429,6 +455,106 @@ def cocg(a, b, tol=1e-8, maxiter=100000, x0=None, history=False, m=None):
         beta = rho_new / rho
         rho = rho_new
         hist.append(np.linalg.norm(r) / nb)
+    rr = float(np.linalg.norm(b - a @ x) / nb)
+    if history:
+        return x, it, rr, np.array(hist)
+    return x, it, rr
+
+
+def cocr(a, b, tol=1e-8, maxiter=100000, history=False):
+    """Conjugate orthogonal conjugate residual method (Sogabe & Zhang, 2007):
+    the conjugate residual recurrences with the unconjugated bilinear form
+    x^T y, valid for complex symmetric A (the paper's "cr", Sec. IV).  Stops
+    when the recursive ``||r|| <= tol ||b||``.  Returns ``(x, iterations,
+    relres)`` and, with ``history``, the recursive relative residual after
+    every iteration."""
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    w = a @ r
+    q = w.copy()
+    rho = r @ w
+    hist = []
+    it = 0
+    while it < maxiter and np.linalg.norm(r) > tol * nb:
+        it += 1
+        alpha = rho / (q @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        hist.append(np.linalg.norm(r) / nb)
+        w = a @ r
+        rho_new = r @ w
+        beta = rho_new / rho
+        rho = rho_new
+        p = r + beta * p
+        q = w + beta * q
+    rr = float(np.linalg.norm(b - a @ x) / nb)
+    if history:
+        return x, it, rr, np.array(hist)
+    return x, it, rr
+
+
+def tfqmr(a, b, rhat, tol=1e-8, maxiter=100000, history=False):
+    """Transpose-free QMR (Freund, 1993) in its half-step form: per
+    iteration two half-steps m (even: new alpha, u_{m+1} = u_m - alpha v_m;
+    both: w -= alpha A u_m, d = u_m + (theta^2/alpha) eta d, theta =
+    ||w||/tau, c = (1+theta^2)^{-1/2}, tau = tau theta c, eta = c^2 alpha,
+    x += eta d; odd: rho' = <rhat, w>, beta = rho'/rho, u_{m+1} = w + beta
+    u_m, v = A u_{m+1} + beta (A u_m + beta v)), with conjugated inner
+    products.  Stops on the QMR bound tau sqrt(m+1) <= tol ||b||.  Returns
+    ``(x, iterations, relres)`` and, with ``history``, the relative bound
+    after every iteration."""
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    w = b.copy()
+    u = b.copy()
+    au = a @ u
+    v = au.copy()
+    d = np.zeros_like(b)
+    tau = nb
+    theta = 0.0
+    eta = 0.0
+    rho = np.vdot(rhat, b)
+    alpha = 0.0
+    hist = []
+    it = 0
+    m = 0
+    while it < maxiter:
+        # even half-step
+        alpha = rho / np.vdot(rhat, v)
+        u_next = u - alpha * v
+        w = w - alpha * au
+        d = u + (theta ** 2 / alpha) * eta * d
+        theta = np.linalg.norm(w) / tau
+        c2 = 1.0 / (1.0 + theta ** 2)
+        tau = tau * theta * np.sqrt(c2)
+        eta = c2 * alpha
+        x = x + eta * d
+        m += 1
+        # odd half-step
+        u = u_next
+        au_odd = a @ u
+        w = w - alpha * au_odd
+        d = u + (theta ** 2 / alpha) * eta * d
+        theta = np.linalg.norm(w) / tau
+        c2 = 1.0 / (1.0 + theta ** 2)
+        tau = tau * theta * np.sqrt(c2)
+        eta = c2 * alpha
+        x = x + eta * d
+        m += 1
+        it += 1
+        bound = tau * np.sqrt(m + 1)
+        hist.append(bound / nb)
+        if bound <= tol * nb:
+            break
+        rho_new = np.vdot(rhat, w)
+        beta = rho_new / rho
+        rho = rho_new
+        u_even = w + beta * u
+        au = a @ u_even
+        v = au + beta * (au_odd + beta * v)
+        u = u_even
     rr = float(np.linalg.norm(b - a @ x) / nb)
     if history:
         return x, it, rr, np.array(hist)

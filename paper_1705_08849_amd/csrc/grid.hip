@@ -5,6 +5,7 @@
 #include <string>
 #include <vector>
 
+#include "diag.h"
 #include "fit_internal.h"
 #include "stencil.h"
 
@@ -356,9 +357,17 @@ extern "C" fit_status fit_edge_mask(const fit_grid* g, uint8_t* mask_dev, void* 
 }
 
 extern "C" fit_status fit_material_diag(const fit_grid* g, int kind, double* out_dev, void* stream) {
-  if (!g || !out_dev || kind < 0 || kind > 2) {
-    set_error("fit_material_diag: NULL argument or kind not in 0..2");
+  if (!g || !out_dev || kind < 0 || kind > 3) {
+    set_error("fit_material_diag: NULL argument or kind not in 0..3");
     return FIT_E_INVALID;
+  }
+  if (kind == 3) {
+    DeviceGuard guard(g->device);
+    const int64_t nb = (g->view.np + 255) / 256;
+    hipLaunchKernelGGL(edge_diag_kernel<double>, dim3((unsigned)nb), dim3(256), 0,
+                       (hipStream_t)stream, g->view, 0.0, (int)ED_CURLCURL, out_dev);
+    FIT_HIP(hipGetLastError());
+    return FIT_OK;
   }
   const int mode = kind == 1 ? MODE_SIGMA : MODE_EPS;
   return launch_node_coef(g, 0.0, mode, nullptr, out_dev, kind == 2 ? 1 : 0, stream);

@@ -16,6 +16,7 @@ static fit_status matvec_typed(const fit_grid* g, double omega, int scaling, con
   OpMatvec<T> op{(const T*)x, (T*)y};
   const TileShape t = tile_for(g, sizeof(T) == 8 ? FIT_C128 : FIT_C64);
   if (scaling == FIT_SCALE_SYM) return launch_stencil<T, MODE_MEC>(g->view, t, omega, op, s);
+  if (scaling == FIT_SCALE_FACT) return launch_stencil<T, MODE_FACT>(g->view, t, omega, op, s);
   return launch_stencil<T, MODE_D>(g->view, t, omega, op, s);
 }
 
@@ -31,12 +32,12 @@ extern "C" fit_status fit_matvec(const fit_grid* g, double omega, int dtype, int
     set_error("fit_matvec: omega must be finite and >= 0");
     return FIT_E_INVALID;
   }
-  if (scaling != FIT_SCALE_NONE && scaling != FIT_SCALE_SYM) {
+  if (scaling != FIT_SCALE_NONE && scaling != FIT_SCALE_SYM && scaling != FIT_SCALE_FACT) {
     set_error("fit_matvec: unknown scaling");
     return FIT_E_INVALID;
   }
-  if (scaling == FIT_SCALE_SYM && omega == 0.0) {
-    set_error("fit_matvec: FIT_SCALE_SYM needs omega > 0");
+  if (scaling != FIT_SCALE_NONE && omega == 0.0) {
+    set_error("fit_matvec: FIT_SCALE_SYM and FIT_SCALE_FACT need omega > 0");
     return FIT_E_INVALID;
   }
   if (x_dev == y_dev) {

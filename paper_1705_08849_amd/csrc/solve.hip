@@ -10,6 +10,7 @@
 #include <mutex>
 #include <vector>
 
+#include "diag.h"
 #include "fit_internal.h"
 #include "krylov.h"
 #include "precond.h"
@@ -339,11 +340,24 @@ struct IdentityPrecond : PrecondApply {
 
 
 // Inner solve in precision T on A_int d = rin (rin has unit norm), from d = 0.
+// COCR vectors: x, r, p, q = A p, w = A r.
+template <class T>
+struct CrVecs {
+  T *x, *r, *p, *q, *w;
+};
+// TFQMR vectors: the even and odd u and their products, w, v, d, shadow.
+template <class T>
+struct TqVecs {
+  T *x, *w, *u0, *u1, *au0, *au1, *v, *d, *rh;
+};
+
 template <class T>
 struct Inner {
   int solver, m;
   BiVecs<T> bv;
   GmVecs<T> gv;
+  CrVecs<T> cr;
+  TqVecs<T> tq;
   T* rin;
   T* d;
   // true: the inner method applies the symmetric scaling itself (as a
@@ -391,12 +405,37 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
   const int64_t nb = pw_blocks(ne);
   // With the symmetric scaling requested, COCG runs on the unscaled operator
   // preconditioned by M = S^2 (z = M r); the iterates equal those of COCG on
-  // S A S, and the operator kernel needs no per-edge square roots.
-  const bool pre = c.sym != 0;
+  // S A S, and the operator kernel needs no per-edge square roots.  A stored
+  // diagonal (c.diag: the mass matrix, the paper's eq. (Precond) or Jacobi)
+  // runs the unfused form instead: z = m .* r kept as a vector.
+  const bool stored = c.diag != 0;
+  const bool pre = !stored && c.sym != 0;
   T* z = V.s;
   T* mdiag = V.t;
   const int64_t nbn = nb;
   const OtfShape otf = otf_shape(c.g->view, c.max_blocks);
+  if (stored) {
+    hipLaunchKernelGGL(edge_diag_kernel<T>, dim3((unsigned)pw_blocks(c.g->view.np)), dim3(256), 0,
+                       c.s, c.g->view, c.omega, c.diag, mdiag);
+    FIT_HIP(hipGetLastError());
+    // COCG's iterates do not change when M is scaled by a constant; scale m
+    // to unit rms so that rho = r^T z keeps the magnitude of r^T r and the
+    // breakdown test (|rho| against ||r||^2) means the same for every
+    // diagonal (1/K_ee is ~1e-11 in SI units, 1/M_eps,c ~1e16)
+    if ((st = xform<T, T, XF_SCALE>(c, false, false, mdiag, mdiag, 1.0, true)) != FIT_OK) return st;
+    if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+    const double m2 = c.h_red->v[0];
+    if (!(m2 > 0.0) || !std::isfinite(m2)) {
+      *done = kNan;
+      return FIT_OK;
+    }
+    if ((st = xform<T, T, XF_SCALE>(c, false, false, mdiag, mdiag, std::sqrt((double)ne / m2), false)) != FIT_OK)
+      return st;
+    hipLaunchKernelGGL((pcocg_update_kernel<T, true>), dim3((unsigned)nbn), dim3(256), 0, c.s, ne,
+                       V.x, V.r, z, V.p[0], q, mdiag, c.cst, c.part);
+    FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<3>(c.part, (int)nbn, PcocgInitFinish{c.cst}, c.s));
+  }
   if (pre) {
     hipLaunchKernelGGL(mass_inverse_kernel<T>, dim3((unsigned)pw_blocks(c.g->view.np)), dim3(256),
                        0, c.s, c.g->view, c.omega, mdiag);
@@ -415,11 +454,15 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
       OpCocgPX<T> k1{V.r, p_old, p_new, q, V.x, c.cst, c.part, (T)(c.omega * c.omega), {}, {}};
       if ((e = launch_op_stencil_mode<T>(c, false, k1)) != FIT_OK) return e;
     } else {
-      OpCocgP<T> k1{V.r, p_old, p_new, q, c.cst, c.part, c.cnt, {}};
+      // p = z + beta p_old (z = r without a preconditioner), q = A p
+      OpCocgP<T> k1{stored ? z : V.r, p_old, p_new, q, c.cst, c.part, c.cnt, {}};
       if ((e = launch_op_stencil_mode<T>(c, false, k1)) != FIT_OK) return e;
     }
     const int tok = prof_begin(c.s);
-    if (pre) {
+    if (stored) {
+      hipLaunchKernelGGL((pcocg_update_kernel<T, false>), dim3((unsigned)nbn), dim3(256), 0, c.s,
+                         ne, V.x, V.r, z, p_new, q, mdiag, c.cst, c.part);
+    } else if (pre) {
       hipLaunchKernelGGL((pcocg_rupdate_otf_kernel<T, kOtfZc>), dim3((unsigned)otf.blocks), dim3(256),
                          0, c.s, c.g->view, c.omega, V.r, q, c.cst, c.part);
     } else {
@@ -431,7 +474,7 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
     FIT_HIP(launch_finish<3>(c.part, (int)(pre ? otf.blocks : nb), CocgFinish{c.cst}, c.s));
     return FIT_OK;
   };
-  const double per_iter_bytes = node_bytes(c.g, pre ? 9 : 10, sizeof(T));
+  const double per_iter_bytes = node_bytes(c.g, stored ? 12 : (pre ? 9 : 10), sizeof(T));
   if (check_every <= 0) check_every = 2 * std::max(1, std::min(100, (int)(4e8 / (double)ne)));
   if (check_every & 1) ++check_every;
   hipGraphExec_t gexec = nullptr;
@@ -506,11 +549,241 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
   return FIT_OK;
 }
 
+// Host side of an iteration whose scalars live in device state S (fields
+// iter, done, rr): replay check_every iterations (a captured graph or eager
+// launches), read the state, count bytes and operator applications, and stop
+// on a stop code or when the residual estimate has not fallen to a quarter
+// within stall_window iterations (reported as a stall through *stalled).
+template <class S, class F>
+static fit_status poll_iterations(Ctx& c, F&& one_iter, int check_every, int use_graph, S* st_dev,
+                                  S* st_host, double per_iter_bytes, int mv_per_iter,
+                                  int stall_window, bool* stalled) {
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (use_graph) {
+    hipStream_t cap = nullptr;
+    FIT_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    const hipStream_t user = c.s;
+    c.s = cap;
+    hipError_t he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    fit_status e = he == hipSuccess ? FIT_OK : hip_fail(he, "hipStreamBeginCapture");
+    for (int k = 0; k < check_every && e == FIT_OK; ++k) e = one_iter();
+    if (he == hipSuccess) he = hipStreamEndCapture(cap, &graph);
+    c.s = user;
+    (void)hipStreamDestroy(cap);
+    if (e != FIT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return e;
+    }
+    if (he != hipSuccess) return hip_fail(he, "hipStreamEndCapture");
+    he = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(he, "hipGraphInstantiate");
+    }
+  }
+  int last_iter = 0, best_at = 0;
+  double best_rr = -1.0;
+  fit_status ret = FIT_OK;
+  *stalled = false;
+  for (;;) {
+    if (use_graph) {
+      const hipError_t he = hipGraphLaunch(gexec, c.s);
+      if (he != hipSuccess) {
+        ret = hip_fail(he, "hipGraphLaunch");
+        break;
+      }
+    } else {
+      for (int k = 0; k < check_every && ret == FIT_OK; ++k) ret = one_iter();
+      if (ret != FIT_OK) break;
+    }
+    if ((ret = sync_copy(c, st_host, st_dev, sizeof(S))) != FIT_OK) break;
+    c.bytes += per_iter_bytes * (st_host->iter - last_iter);
+    c.matvecs += mv_per_iter * (st_host->iter - last_iter);
+    last_iter = st_host->iter;
+    if (st_host->done != kRunning) break;
+    if (best_rr < 0.0 || st_host->rr < 0.25 * best_rr) {
+      best_rr = st_host->rr;
+      best_at = st_host->iter;
+    } else if (st_host->iter - best_at >= stall_window) {
+      *stalled = true;
+      break;
+    }
+  }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+  return ret;
+}
+
+// COCR (the paper's CR in complex symmetric form) on A_int x = r, from
+// x = 0; r is overwritten.
+
+template <class T>
+static fit_status cocr(Ctx& c, CrVecs<T>& V, double tol_rel, int max_iter, int check_every,
+                       double hscale, double* hist_dev, int hist_len, int use_graph, int* done,
+                       int* iters) {
+  const int64_t ne = c.g->ne;
+  const int64_t nb = pw_blocks(ne);
+  fit_status st;
+  if ((st = vzero(c, V.x, ne)) != FIT_OK) return st;
+  if ((st = vzero(c, V.p, ne)) != FIT_OK) return st;
+  if ((st = vzero(c, V.q, ne)) != FIT_OK) return st;
+  hipLaunchKernelGGL((dot_kernel<T, true>), dim3((unsigned)nb), dim3(256), 0, c.s, V.r, V.r, ne,
+                     c.red, c.part, c.cnt);
+  FIT_HIP(hipGetLastError());
+  FIT_HIP(launch_finish<4>(c.part, (int)nb, StoreSums<4>{c.red}, c.s));
+  if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+  const double r0 = c.h_red->v[2];
+  *iters = 0;
+  if (!(r0 > 0.0) || !std::isfinite(r0)) {
+    *done = r0 == 0.0 ? kConverged : kNan;
+    return FIT_OK;
+  }
+  CgState h{};
+  h.rr = r0;
+  h.tol2 = tol_rel * tol_rel * r0;
+  h.hscale = hscale / std::sqrt(r0);
+  h.max_iter = max_iter;
+  h.done = kRunning;
+  h.hist = hist_dev;
+  h.hist_len = hist_len;
+  FIT_HIP(hipMemcpyAsync(c.cst, &h, sizeof(CgState), hipMemcpyHostToDevice, c.s));
+  // w = A r, rho = r^T w
+  OpCocrW<T> k0{V.r, V.w, c.cst, c.part, c.cnt, 1};
+  if ((st = launch_op_stencil_mode<T>(c, c.sym, k0)) != FIT_OK) return st;
+  auto one_iter = [&]() -> fit_status {
+    const int tok = prof_begin(c.s);
+    hipLaunchKernelGGL(cocr_pq_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.r, V.w, V.p,
+                       V.q, c.cst, c.part);
+    FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<2>(c.part, (int)nb, CocrAlphaFinish{c.cst}, c.s));
+    hipLaunchKernelGGL(cocr_xr_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.x, V.r, V.p,
+                       V.q, c.cst, c.part);
+    FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<1>(c.part, (int)nb, CocrResFinish{c.cst}, c.s));
+    prof_end(tok, c.s, sizeof(T) == 8 ? "cocr_update_c128" : "cocr_update_c64");
+    OpCocrW<T> k1{V.r, V.w, c.cst, c.part, c.cnt, 0};
+    return launch_op_stencil_mode<T>(c, c.sym, k1);
+  };
+  // operator 2 passes, p/q update 6, x/r update 6
+  const double per_iter_bytes = node_bytes(c.g, 14, sizeof(T));
+  if (check_every <= 0) check_every = 2 * std::max(1, std::min(100, (int)(4e8 / (double)ne)));
+  bool stalled = false;
+  const int stall_window = sizeof(T) == 4 ? 4000 : 30000;
+  if ((st = poll_iterations(c, one_iter, check_every, use_graph, c.cst, c.h_cst, per_iter_bytes, 1,
+                            stall_window, &stalled)) != FIT_OK)
+    return st;
+  *done = stalled ? kBreakdown : c.h_cst->done;
+  *iters = c.h_cst->iter;
+  c.last_reason = stalled ? 9 : c.h_cst->reason;
+  c.last_rr = c.h_cst->rr / r0;
+  return FIT_OK;
+}
+
+// TFQMR on A_int x = r0v from x = 0.
+
+template <class T>
+static fit_status tfqmr(Ctx& c, TqVecs<T>& V, const T* r0v, double tol_rel, int max_iter,
+                        int check_every, double hscale, double* hist_dev, int hist_len,
+                        int use_graph, uint64_t shadow_seed, int* done, int* iters) {
+  const int64_t ne = c.g->ne;
+  const int64_t nb = pw_blocks(ne);
+  fit_status st;
+  if ((st = vzero(c, V.x, ne)) != FIT_OK) return st;
+  if ((st = vzero(c, V.d, ne)) != FIT_OK) return st;
+  if ((st = vcopy(c, r0v, V.w, ne)) != FIT_OK) return st;
+  if ((st = vcopy(c, r0v, V.u0, ne)) != FIT_OK) return st;
+  // dense pseudo-random shadow vector (as for BiCGStab), rho = <rh, r0>
+  if ((st = xform<T, T, XF_SHADOW>(c, false, false, V.w, V.rh, 1.0, false, shadow_seed)) != FIT_OK)
+    return st;
+  hipLaunchKernelGGL(dot_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, V.rh, V.w, ne, c.red,
+                     c.part, c.cnt);
+  FIT_HIP(hipGetLastError());
+  FIT_HIP(launch_finish<4>(c.part, (int)nb, StoreSums<4>{c.red}, c.s));
+  if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+  const double r0 = c.h_red->v[3];
+  *iters = 0;
+  if (!(r0 > 0.0) || !std::isfinite(r0)) {
+    *done = r0 == 0.0 ? kConverged : kNan;
+    return FIT_OK;
+  }
+  TqState h{};
+  h.rho = cx<double>{c.h_red->v[0], c.h_red->v[1]};
+  h.tau = std::sqrt(r0);
+  h.rr = r0;
+  h.tol2 = tol_rel * tol_rel * r0;
+  h.hscale = hscale / std::sqrt(r0);
+  h.max_iter = max_iter;
+  h.done = kRunning;
+  h.hist = hist_dev;
+  h.hist_len = hist_len;
+  FIT_HIP(hipMemcpyAsync(c.tst, &h, sizeof(TqState), hipMemcpyHostToDevice, c.s));
+  const int* dflag = &c.tst->done;
+  {  // v = A u0, kept as A u0 too
+    OpMatvecIf<T> mv{V.u0, V.au0, dflag};
+    if ((st = launch_op_stencil_mode<T>(c, c.sym, mv)) != FIT_OK) return st;
+    if ((st = vcopy(c, V.au0, V.v, ne)) != FIT_OK) return st;
+  }
+  auto one_iter = [&]() -> fit_status {
+    fit_status e;
+    const int tok = prof_begin(c.s);
+    // even half-step: alpha = rho / <rh, v>; u1 = u0 - alpha v; w -= alpha A u0
+    hipLaunchKernelGGL(tq_dot_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.rh, V.v,
+                       c.tst, c.part);
+    FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<2>(c.part, (int)nb, TqAlphaFinish{c.tst}, c.s));
+    hipLaunchKernelGGL((tq_half_kernel<T, true>), dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.u0,
+                       V.u1, V.v, V.w, V.au0, V.d, c.tst, c.part);
+    FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<1>(c.part, (int)nb, TqStepFinish{c.tst}, c.s));
+    hipLaunchKernelGGL((tq_x_kernel<T, false>), dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.x,
+                       V.d, V.rh, V.w, c.tst, c.part);
+    FIT_HIP(hipGetLastError());
+    prof_end(tok, c.s, sizeof(T) == 8 ? "tfqmr_update_c128" : "tfqmr_update_c64");
+    // odd half-step: w -= alpha A u1, x update, rho' = <rh, w>, beta
+    OpMatvecIf<T> m1{V.u1, V.au1, dflag};
+    if ((e = launch_op_stencil_mode<T>(c, c.sym, m1)) != FIT_OK) return e;
+    hipLaunchKernelGGL((tq_half_kernel<T, false>), dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.u1,
+                       V.u1, V.v, V.w, V.au1, V.d, c.tst, c.part);
+    FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<1>(c.part, (int)nb, TqStepFinish{c.tst}, c.s));
+    hipLaunchKernelGGL((tq_x_kernel<T, true>), dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.x, V.d,
+                       V.rh, V.w, c.tst, c.part);
+    FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<2>(c.part, (int)nb, TqRhoFinish{c.tst}, c.s));
+    // next u0 = w + beta u1, its product, and v = A u0 + beta (A u1 + beta v)
+    hipLaunchKernelGGL(tq_u_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.u0, V.w, V.u1,
+                       c.tst);
+    FIT_HIP(hipGetLastError());
+    OpMatvecIf<T> m0{V.u0, V.au0, dflag};
+    if ((e = launch_op_stencil_mode<T>(c, c.sym, m0)) != FIT_OK) return e;
+    hipLaunchKernelGGL(tq_v_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.v, V.au0,
+                       V.au1, c.tst);
+    FIT_HIP(hipGetLastError());
+    return FIT_OK;
+  };
+  // two operator applications (4 passes) and about 27 vector passes
+  const double per_iter_bytes = node_bytes(c.g, 31, sizeof(T));
+  if (check_every <= 0) check_every = 2 * std::max(1, std::min(50, (int)(2e8 / (double)ne)));
+  bool stalled = false;
+  const int stall_window = sizeof(T) == 4 ? 1500 : 6000;
+  if ((st = poll_iterations(c, one_iter, check_every, use_graph, c.tst, c.h_tst, per_iter_bytes, 2,
+                            stall_window, &stalled)) != FIT_OK)
+    return st;
+  *done = stalled ? kBreakdown : c.h_tst->done;
+  *iters = c.h_tst->iter;
+  c.last_reason = stalled ? 9 : c.h_tst->reason;
+  c.last_rr = c.h_tst->rr / r0;
+  return FIT_OK;
+}
+
 template <class T>
 static size_t inner_bytes(int64_t ne, int solver, int m) {
   const size_t v = align_up((size_t)ne * 2 * sizeof(T), 256);
   if (solver == FIT_BICGSTAB) return 11 * v;
   if (solver == FIT_COCG) return 8 * v;
+  if (solver == FIT_COCR) return 6 * v;
+  if (solver == FIT_TFQMR) return 10 * v;
   const int nblk = (int)((ne + 256 * kMdPer - 1) / (256 * kMdPer));
   return (size_t)(2 * m + 5) * v + align_up(sizeof(double) * 2 * (size_t)(m + 1) * nblk, 256);
 }
@@ -544,6 +817,24 @@ static void inner_carve(Arena& a, Inner<T>& in, int64_t ne, int solver, int m) {
     in.bv.rh = in.bv.v[1] = nullptr;
     in.d = in.bv.x;
     in.own_scaling = true;
+  } else if (solver == FIT_COCR) {
+    in.cr.x = a.take<T>(v);
+    in.cr.r = a.take<T>(v);
+    in.cr.p = a.take<T>(v);
+    in.cr.q = a.take<T>(v);
+    in.cr.w = a.take<T>(v);
+    in.d = in.cr.x;
+  } else if (solver == FIT_TFQMR) {
+    in.tq.x = a.take<T>(v);
+    in.tq.w = a.take<T>(v);
+    in.tq.u0 = a.take<T>(v);
+    in.tq.u1 = a.take<T>(v);
+    in.tq.au0 = a.take<T>(v);
+    in.tq.au1 = a.take<T>(v);
+    in.tq.v = a.take<T>(v);
+    in.tq.d = a.take<T>(v);
+    in.tq.rh = a.take<T>(v);
+    in.d = in.tq.x;
   } else {
     const size_t vv = align_up(v, 256);
     in.gv.ldv = (int64_t)(vv / (2 * sizeof(T)));
@@ -575,6 +866,17 @@ static fit_status run_inner(Ctx& c, Inner<T>& in, double q, int max_iter, int ch
     if (st != FIT_OK) return st;
     return cocg<T>(c, in.bv, q, max_iter, check_every, hscale, hist, hist_len, use_graph, done,
                    iters);
+  }
+  if (in.solver == FIT_COCR) {
+    fit_status st = vcopy<T>(c, in.rin, in.cr.r, c.g->ne);
+    if (st != FIT_OK) return st;
+    return cocr<T>(c, in.cr, q, max_iter, check_every, hscale, hist, hist_len, use_graph, done,
+                   iters);
+  }
+  if (in.solver == FIT_TFQMR) {
+    const uint64_t seed = kShadowSeed + (uint64_t)in.restarts++;
+    return tfqmr<T>(c, in.tq, in.rin, q, max_iter, check_every, hscale, hist, hist_len, use_graph,
+                    seed, done, iters);
   }
   return gmres<T>(c, in.gv, in.m, q, max_iter, hscale, hist, hist_len, pre, in.rin, nullptr,
                   done, iters, &tmp, 0.0);
@@ -613,7 +915,7 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
   // is spent: a correction that does not lower the true residual is undone
   // and the next inner solve starts again from the best iterate.  Only a
   // long run of inner solves without halving the residual ends it early.
-  const bool retry = in.solver == FIT_BICGSTAB;
+  const bool retry = in.solver == FIT_BICGSTAB || in.solver == FIT_TFQMR;
   const int max_no_progress = retry ? (sizeof(T) == 4 ? 6 : 64) : 4;
   for (;;) {
     // inner rhs: S r scaled to unit norm, in precision T (S r = eta * rin)
@@ -737,12 +1039,17 @@ extern "C" fit_status fit_solve(fit_grid* g, double omega, const void* source_de
   if (opts) o = *opts;
   if (o.restart == 0) o.restart = 30;
   if (o.max_iters <= 0) o.max_iters = 100000;
-  if (o.solver < FIT_BICGSTAB || o.solver > FIT_COCG || o.restart < 1 ||
+  if (o.solver < FIT_BICGSTAB || o.solver > FIT_TFQMR || o.restart < 1 ||
       o.restart > kMaxRestart || (o.precision != FIT_PREC_FP64 && o.precision != FIT_PREC_MIXED) ||
       (o.scaling != FIT_SCALE_NONE && o.scaling != FIT_SCALE_SYM) || o.resid_history_len < 0 ||
-      (o.resid_history_len > 0 && !o.resid_history)) {
+      (o.resid_history_len > 0 && !o.resid_history) || o.diag < FIT_DIAG_AUTO ||
+      o.diag > FIT_DIAG_JACOBI) {
     set_error("fit_solve: invalid options");
     return FIT_E_INVALID;
+  }
+  if (o.diag != FIT_DIAG_AUTO && o.solver != FIT_COCG) {
+    set_error("fit_solve: a stored diagonal preconditioner (opts.diag) is implemented for FIT_COCG only");
+    return FIT_E_UNSUPPORTED;
   }
   if (o.inner_tol <= 0.0) o.inner_tol = 1e-4;
   DeviceScope dev(g->device);
@@ -750,6 +1057,7 @@ extern "C" fit_status fit_solve(fit_grid* g, double omega, const void* source_de
   Ctx c;
   fit_status st = setup_ctx(c, g, omega, o.scaling == FIT_SCALE_SYM, s);
   if (st != FIT_OK) return st;
+  c.diag = o.diag;
 
   const int64_t ne = g->ne;
   const size_t v128 = align_up((size_t)ne * 16, 256);

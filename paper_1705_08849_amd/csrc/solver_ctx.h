@@ -7,6 +7,7 @@
 
 #include "fit_internal.h"
 #include "krylov.h"
+#include "krylov_more.h"
 #include "solver_kernels.h"
 #include "stencil.h"
 #include "tuning.h"
@@ -21,6 +22,7 @@ struct Ctx {
   hipStream_t s;
   double omega;
   int sym;
+  int diag = 0;  // COCG: fit_diag kind of a stored diagonal preconditioner (0: none stored)
   // reduction scratch
   double* part;
   unsigned* cnt;
@@ -32,6 +34,8 @@ struct Ctx {
   GmState* h_gst;
   CgState* cst = nullptr;
   CgState* h_cst = nullptr;
+  TqState* tst = nullptr;
+  TqState* h_tst = nullptr;
   int max_blocks;
   double bytes = 0.0;  // algorithmic bytes launched
   int matvecs = 0;
@@ -119,7 +123,8 @@ inline fit_status setup_ctx(Ctx& c, fit_grid* g, double omega, int sym, hipStrea
   c.max_blocks = std::max(std::max(b128, b64), 4096);
   const size_t need = align_up(sizeof(double) * 4 * (size_t)c.max_blocks, 256) + 256 +
                       align_up(sizeof(RedOut), 256) + align_up(sizeof(BiState), 256) +
-                      align_up(sizeof(GmState), 256) + align_up(sizeof(CgState), 256);
+                      align_up(sizeof(GmState), 256) + align_up(sizeof(CgState), 256) +
+                      align_up(sizeof(TqState), 256);
   fit_status st = ensure_ws(g->red, need, g->device);
   if (st != FIT_OK) return st;
   char* p = (char*)g->red.ptr;
@@ -134,15 +139,18 @@ inline fit_status setup_ctx(Ctx& c, fit_grid* g, double omega, int sym, hipStrea
   c.gst = (GmState*)p;
   p += align_up(sizeof(GmState), 256);
   c.cst = (CgState*)p;
+  p += align_up(sizeof(CgState), 256);
+  c.tst = (TqState*)p;
   if (!g->pinned) {
     FIT_HIP(hipHostMalloc(&g->pinned, sizeof(RedOut) + sizeof(BiState) + sizeof(GmState) +
-                                          sizeof(CgState) + 256));
+                                          sizeof(CgState) + sizeof(TqState) + 256));
   }
   char* hp = (char*)g->pinned;
   c.h_red = (RedOut*)hp;
   c.h_bst = (BiState*)(hp + sizeof(RedOut));
   c.h_gst = (GmState*)(hp + sizeof(RedOut) + sizeof(BiState));
   c.h_cst = (CgState*)(hp + sizeof(RedOut) + sizeof(BiState) + sizeof(GmState));
+  c.h_tst = (TqState*)(hp + sizeof(RedOut) + sizeof(BiState) + sizeof(GmState) + sizeof(CgState));
   // ticket counter starts at zero; the red block's flag too
   FIT_HIP(hipMemsetAsync(c.cnt, 0, 256, s));
   FIT_HIP(hipMemsetAsync(c.red, 0, sizeof(RedOut), s));

@@ -46,7 +46,12 @@
 
 namespace fit {
 
-enum CoefMode { MODE_D = 0, MODE_MEC = 1, MODE_EPS = 2, MODE_SIGMA = 3 };
+// MODE_D: unscaled operator (staged diagonal d); MODE_MEC: symmetric scaling
+// (staged s = M_eps,c^{-1/2}); MODE_FACT: the same scaled operator evaluated
+// in the factorized order of eq. (e2tt), calA^T (calA x) - omega^2 x with
+// calA = M_mu^{-1/2} C M_eps,c^{-1/2} (each facet flux is scaled by
+// sqrt(M_nu) on the way out of the curl and again on the way back).
+enum CoefMode { MODE_D = 0, MODE_MEC = 1, MODE_EPS = 2, MODE_SIGMA = 3, MODE_FACT = 4 };
 
 template <class T>
 __device__ __forceinline__ void fill_mat_mode(MatLds<T>& m, const MatEntry* mats, double omega,
@@ -57,7 +62,7 @@ __device__ __forceinline__ void fill_mat_mode(MatLds<T>& m, const MatEntry* mats
     if (mode == MODE_D) {
       cre = -omega * omega * e.eps;
       cim = omega * omega * e.eps_tand + omega * e.sigma;
-    } else if (mode == MODE_MEC) {
+    } else if (mode == MODE_MEC || mode == MODE_FACT) {
       cre = e.eps;
       cim = omega > 0.0 ? -(e.eps_tand + e.sigma / omega) : 0.0;
     } else if (mode == MODE_EPS) {
@@ -75,7 +80,8 @@ __device__ __forceinline__ void fill_mat_mode(MatLds<T>& m, const MatEntry* mats
 template <class T>
 __host__ __device__ __forceinline__ cx<T> port_coef_mode(double omega, int mode) {
   if (mode == MODE_D) return cx<T>{T(0), (T)omega};
-  if (mode == MODE_MEC) return cx<T>{T(0), omega > 0.0 ? (T)(-1.0 / omega) : T(0)};
+  if (mode == MODE_MEC || mode == MODE_FACT)
+    return cx<T>{T(0), omega > 0.0 ? (T)(-1.0 / omega) : T(0)};
   if (mode == MODE_SIGMA) return cx<T>{T(1), T(0)};
   return cx<T>{T(0), T(0)};
 }
@@ -144,7 +150,7 @@ __device__ __forceinline__ void stage_node(Staged<T>& st, const cx<T> (&xin)[3],
     const bool fr = (nc.mask >> w) & 1u;
     cx<T> xv = fr ? xin[w] : cx<T>{T(0), T(0)};
     st.xr[w] = xv;
-    if (MODE == MODE_MEC) {
+    if (MODE == MODE_MEC || MODE == MODE_FACT) {
       cx<T> s = fr ? crsqrt(nc.e[w]) : cx<T>{T(0), T(0)};
       st.cf[w] = s;
       st.xs[w] = s * xv;
@@ -152,7 +158,8 @@ __device__ __forceinline__ void stage_node(Staged<T>& st, const cx<T> (&xin)[3],
       st.cf[w] = fr ? nc.e[w] : cx<T>{T(0), T(0)};
       st.xs[w] = xv;
     }
-    st.nu[w] = nc.nu[w];
+    // MODE_FACT stages M_mu^{-1/2}: each facet flux is scaled by it twice
+    st.nu[w] = MODE == MODE_FACT ? sqrt(nc.nu[w]) : nc.nu[w];
   }
   st.mask = nc.mask;
 }
@@ -192,7 +199,8 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
   constexpr int TX = BX - 2, TY = BY - 2;
   constexpr int NT = BX * BY;
   static_assert(NT % 64 == 0, "whole wavefronts");
-  constexpr bool SYM = (MODE == MODE_MEC);
+  constexpr bool SYM = (MODE == MODE_MEC || MODE == MODE_FACT);
+  constexpr bool FACT = (MODE == MODE_FACT);
   constexpr int NR = Op::NRED > 0 ? Op::NRED : 1;
 
   op.begin();
@@ -344,6 +352,12 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
       hx = cur_nu[0] * (xz_jp - xo[2] - sn.xs[1] + xo[1]);
       hy = cur_nu[1] * (sn.xs[0] - xo[0] - xz_ip + xo[2]);
       hz = cur_nu[2] * (xy_ip - xo[1] - xx_jp + xo[0]);
+      if (FACT) {
+        // t = calA x on the facet, then M_mu^{-1/2} t enters calA^T
+        hx = cur_nu[0] * hx;
+        hy = cur_nu[1] * hy;
+        hz = cur_nu[2] * hz;
+      }
       H[b][0][ty][tx] = hx;
       H[b][1][ty][tx] = hy;
       H[b][2][ty][tx] = hz;

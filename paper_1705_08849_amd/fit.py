@@ -22,13 +22,16 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_NOT_CONVERGED, E_BREAKDOWN, E_NAN, E_UNSUPPO
 STATUS_NAMES = ["FIT_OK", "FIT_E_INVALID", "FIT_E_NOMEM", "FIT_E_DEVICE", "FIT_E_NOT_CONVERGED",
                 "FIT_E_BREAKDOWN", "FIT_E_NAN", "FIT_E_UNSUPPORTED"]
 C128, C64 = 0, 1
-SCALE_NONE, SCALE_SYM = 0, 1
-BICGSTAB, GMRES, FGMRES, COCG = 0, 1, 2, 3
+SCALE_NONE, SCALE_SYM, SCALE_FACT = 0, 1, 2
+BICGSTAB, GMRES, FGMRES, COCG, COCR, TFQMR = 0, 1, 2, 3, 4, 5
 PREC_FP64, PREC_MIXED = 0, 1
+DIAG_AUTO, DIAG_MASS, DIAG_PAPER, DIAG_JACOBI = 0, 1, 2, 3
 
-SOLVERS = {"bicgstab": BICGSTAB, "gmres": GMRES, "fgmres": FGMRES, "cocg": COCG}
-SCALINGS = {"none": SCALE_NONE, "sym": SCALE_SYM}
+SOLVERS = {"bicgstab": BICGSTAB, "gmres": GMRES, "fgmres": FGMRES, "cocg": COCG, "cocr": COCR,
+           "tfqmr": TFQMR}
+SCALINGS = {"none": SCALE_NONE, "sym": SCALE_SYM, "fact": SCALE_FACT}
 PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
+DIAGS = {"auto": DIAG_AUTO, "mass": DIAG_MASS, "paper": DIAG_PAPER, "jacobi": DIAG_JACOBI}
 
 
 class FitError(RuntimeError):
@@ -60,7 +63,7 @@ class SolveOpts(C.Structure):
                 ("check_every", C.c_int32), ("precision", C.c_int32), ("scaling", C.c_int32),
                 ("inner_tol", C.c_double), ("precond", C.c_void_p), ("stream", C.c_void_p),
                 ("resid_history", C.POINTER(C.c_double)), ("resid_history_len", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("diag", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -300,7 +303,7 @@ class Grid:
               restart: int = 30, max_iters: int = 0, check_every: int = 0,
               precision: str = "fp64", scaling: str = "sym", inner_tol: float = 0.0,
               precond=None, history: int = 0, use_graph: bool = False, x=None,
-              stream=None, raise_on_error: bool = True):
+              stream=None, raise_on_error: bool = True, diag: str = "auto"):
         """Solve ``A(omega) e = -j omega j`` (``source`` = j, complex128 on the
         device).  Returns ``(e, info_dict)``."""
         torch = _torch()
@@ -313,7 +316,7 @@ class Grid:
                          C.c_void_p(precond.h.value if precond is not None else None),
                          _stream_ptr(stream),
                          C.cast(hist, C.POINTER(C.c_double)) if hist else None,
-                         history, int(bool(use_graph)))
+                         history, int(bool(use_graph)), DIAGS[diag])
         info = SolveInfo()
         st = lib().fit_solve(self.h, float(omega), _dptr(source), float(tol), C.byref(opts),
                              _dptr(x), C.byref(info))

@@ -354,6 +354,57 @@ def test_sym_scaled_operator_has_unit_mass():
     np.testing.assert_allclose(lam, np.sort(ref), rtol=1e-9, atol=1e-9 * ref.max())
 
 
+# --- The paper's factorized form and its diagonal preconditioner ------------
+
+@pytest.mark.parametrize("walls", [0x3F, 0b000000, 0b010110])
+def test_paper_diagonal_preconditioner_closed_form(walls):
+    """Eq. (Precond) on a homogeneous box of uniform cells: every free edge
+    along axis w has P = 2 c^2 / eps_r * sum over the two other axes a of
+    1/h_a^2, also at open walls (half dual cells halve both the facet
+    reluctances and the edge's permittivity integral)."""
+    hs = (1.0e-3, 1.3e-3, 0.7e-3)
+    dev = D.cavity(4, 3, 5, *hs, eps_r=2.5)
+    dev.pec_walls = walls
+    om = 2 * np.pi * 7e9
+    p = O.paper_diag_preconditioner(dev, om)
+    w = (np.arange(dev.n_edges) % 3)[O.free_edges(dev)]
+    inv2 = np.array([1 / h ** 2 for h in hs])
+    ref = 2 * O.C0 ** 2 / 2.5 * (inv2.sum() - inv2[w])
+    np.testing.assert_allclose(p, ref, rtol=1e-12)
+
+
+def test_factorized_form_equals_the_scaled_operator():
+    """Eq. (e2tt): calA^T calA - omega^2 I is S A S (eq. (e2t)); the column
+    sums of calA's squares are the diagonal of S K S."""
+    dev = D.layered_device(9, 8, 6, n_layers=3, n_strips=1, n_ports=1, seed=3)
+    om = 2 * np.pi * 11e9
+    x = (np.random.default_rng(4).uniform(-1, 1, dev.n_edges)
+         + 1j * np.random.default_rng(5).uniform(-1, 1, dev.n_edges)) * O.free_edges(dev)
+    y_fact = O.matvec(dev, om, x, scaling="fact")
+    y_sym = O.matvec(dev, om, x, scaling="sym")
+    assert np.linalg.norm(y_fact - y_sym) <= 1e-13 * np.linalg.norm(y_sym)
+    f = O.free_edges(dev)
+    kd = O.stiffness(dev).diagonal()[f]
+    s = O.sym_scaling(dev, om)
+    np.testing.assert_allclose(O.paper_diag_preconditioner(dev, om), kd * s * s, rtol=1e-13)
+
+
+def test_paper_preconditioned_cocg_is_unscaled_cocg_with_inverse_curl_diagonal():
+    """COCG on S A S preconditioned by 1/P produces the iterates of COCG on
+    A preconditioned by S (1/P) S = 1/K_ee (x = S x_hat)."""
+    dev = D.layered_device(10, 9, 8, n_layers=3, n_strips=1, n_ports=1, seed=11)
+    om = 2 * np.pi * 7e9
+    s = O.sym_scaling(dev, om)
+    a0 = O.system_matrix(dev, om)
+    b0 = O.rhs(dev, om, D.port_source(dev, 0))
+    p = O.paper_diag_preconditioner(dev, om)
+    xs, _, _, hs = O.cocg(sp.diags(s) @ a0 @ sp.diags(s), s * b0, tol=1e-30, maxiter=40,
+                          history=True, m=1.0 / p)
+    kd = O.stiffness(dev).diagonal()[O.free_edges(dev)]
+    xu, _, _, hu = O.cocg(a0, b0, tol=1e-30, maxiter=40, history=True, m=1.0 / kd)
+    assert np.linalg.norm(xu - s * xs) <= 1e-8 * np.linalg.norm(xu)
+
+
 # --- Solves ------------------------------------------------------------------
 
 @pytest.mark.parametrize("graded", [False, True])
@@ -640,3 +691,54 @@ def test_edge_count_reading_matches_the_paper():
             assert c.shape == (ne, ne)
             dev = D.cavity(nx - 1, ny - 1, nz - 1)
             assert dev.n_edges == ne
+
+
+def test_mutation_scaled_curl_without_square_root_is_caught(monkeypatch):
+    """calA built with M_nu instead of M_nu^{1/2}: only the closed form of
+    eq. (Precond) notices."""
+    def bad(dev, omega):
+        nx, ny, nz = dev.nodes
+        f = O.free_edges(dev)
+        c = O.curl(nx, ny, nz).astype(np.float64).tocsc()[:, f]
+        return (sp.diags(O.facet_reluctance(dev)) @ c @ sp.diags(O.sym_scaling(dev, omega))).tocsr()
+
+    monkeypatch.setattr(O, "scaled_curl", bad)
+    with pytest.raises(AssertionError):
+        test_paper_diagonal_preconditioner_closed_form(0x3F)
+
+
+@pytest.mark.parametrize("method", ["cocr", "tfqmr"])
+def test_cocr_and_tfqmr_reach_the_direct_solution(method):
+    """The two further methods of the paper's solver comparison (Sec. IV:
+    CR in complex symmetric form, and TFQMR) on a small lossy graded device,
+    scaled as in eq. (e2t): the iterate reaches the sparse direct solution."""
+    dev = D.layered_device(9, 8, 7, n_layers=3, n_strips=1, n_ports=1, seed=13)
+    om = 2 * np.pi * 9e9
+    s = O.sym_scaling(dev, om)
+    a = (sp.diags(s) @ O.system_matrix(dev, om) @ sp.diags(s)).tocsr()
+    src = D.port_source(dev, 0)
+    b = s * O.rhs(dev, om, src)
+    if method == "cocr":
+        x, it, rr = O.cocr(a, b, tol=1e-11)
+    else:
+        x, it, rr = O.tfqmr(a, b, O.shadow_vector(dev.n_edges)[O.free_edges(dev)], tol=1e-11)
+    ref = O.solve_direct(dev, om, src)[O.free_edges(dev)]
+    assert rr <= 1e-9
+    assert np.linalg.norm(s * x - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_cocr_minimises_the_residual_on_a_hermitian_positive_system():
+    """On a real symmetric positive definite matrix COCR is CR, which
+    minimises ||b - A x|| over the Krylov space: its residual norms never
+    increase and, after k steps, do not exceed GMRES(k)'s by more than
+    rounding."""
+    rng = np.random.default_rng(3)
+    q, _ = np.linalg.qr(rng.standard_normal((60, 60)))
+    a = (q * np.linspace(1, 50, 60)) @ q.T
+    b = rng.standard_normal(60).astype(np.complex128)
+    _, _, _, h = O.cocr(sp.csr_matrix(a.astype(np.complex128)), b, tol=1e-14, maxiter=25,
+                        history=True)
+    assert np.all(np.diff(h) <= 1e-12)
+    for k in (5, 10, 20):
+        _, _, rg = O.gmres(sp.csr_matrix(a.astype(np.complex128)), b, restart=k, tol=1e-16, maxiter=k)
+        assert h[k - 1] <= rg * (1 + 1e-8)
