@@ -162,7 +162,11 @@ typedef struct {
                           the stopping test always uses the unscaled system */
   double inner_tol;    /* FIT_PREC_MIXED: relative tolerance of each inner solve
                           (0 -> 1e-4) */
-  struct fit_precond *precond; /* FIT_FGMRES: learned right preconditioner, or NULL */
+  struct fit_precond *precond; /* FIT_FGMRES: learned right preconditioner, or NULL.
+                                  With one, a run whose restart residual has not
+                                  halved within 10 cycles falls back to the
+                                  mass-preconditioned FIT_COCG from the current
+                                  iterate (info.fell_back = 1) */
   void *stream;        /* hipStream_t for all work of the call */
   double *resid_history; /* optional host array: recursive residual estimate
                             (relative) after each iteration */
@@ -396,23 +400,43 @@ typedef struct {
   int32_t steps;         /* optimiser steps (2000) */
   int32_t batch;         /* residual->error pairs per step (4) */
   int32_t crop;          /* crop edge in nodes, multiple of 4 (32) */
-  int32_t pairs_per_system; /* reserved (0) */
+  int32_t pairs_per_system; /* > 0: solver-generated pairs per (grid, omega); 0: noise pairs */
   int32_t seed;          /* initial weights and sampling */
   double lr;             /* Adam learning rate (1e-3) */
   double weight_decay;   /* added to the gradient as weight_decay * w (0) */
   void *stream;
 } fit_precond_cfg;
 
-/* Train a new preconditioner with Adam on residual->error pairs r = A(omega) e,
- * where e is seeded complex noise on the free edges of one of the training
- * grids, smoothed 2, 4, 8 or 16 times by averaging each edge value with the
- * same component at the neighbouring nodes; one pair per sample, on a random
- * crop of `crop` nodes per axis, at a random omega of `omegas`.  Loss: the mean
+/* Train a new preconditioner with Adam on residual->error pairs r = A(omega) e.
+ * With cfg->pairs_per_system = P > 0 the pairs are generated by the solver
+ * (fit_precond_harvest): for every training grid and every omega of `omegas`,
+ * P pairs e = x* - x_k, r = A e from COCG iterates x_k of the grid's port
+ * excitation (port index = (grid index + omega index) mod nports; every
+ * training grid needs a port), harvested once before the first step.  With
+ * P = 0, e is seeded complex noise on the free edges smoothed 2, 4, 8 or 16
+ * times by averaging each edge value with the same component at the
+ * neighbouring nodes.  One pair per sample, on a random crop of `crop` nodes
+ * per axis (at a random omega of `omegas` for noise pairs).  Loss: the mean
  * over the crop's free edges of |U(r/s_r) - e/s_e|^2 with s_r, s_e the rms of
  * r and e there.  Synchronous; *out receives the trained object.  The mean
  * loss of every optimiser step is kept for fit_precond_train_history. */
 fit_status fit_precond_train(struct fit_grid *const *train, int ntrain, const double *omegas,
                              int nomega, const fit_precond_cfg *cfg, struct fit_precond **out);
+/* The solver-generated training pairs (the paper's excitation, Sec. IV: 1 A
+ * on every edge of a lumped port): on grid g at omega with the source j = 1 A
+ * on every edge of port `port`, COCG (complex128, symmetric scaling) runs to
+ * the true relative residual tol, giving x*; a second identical run keeps its
+ * iterate x_k every iterations/(npairs+1) iterations; then e_k = x* - x_k and
+ * r_k = A(omega) e_k (= b - A x_k up to rounding).
+ *   e_dev, r_dev: npairs * n_e complex128 each on the grid's device (pair k at
+ *                 k * n_e); *made receives the number of pairs written (fewer
+ *                 than npairs when the solve ends early); *iterations (may be
+ *                 NULL) the first solve's COCG iterations.
+ * FIT_E_INVALID for NULL pointers, npairs < 1, a port index outside the grid's
+ * ports, omega <= 0 or tol outside (0, 1); the solve's own status if it does
+ * not converge.  Allocates three work vectors.  Synchronous. */
+fit_status fit_precond_harvest(struct fit_grid *g, double omega, int port, int npairs, double tol,
+                               void *e_dev, void *r_dev, int *made, int *iterations);
 /* Per-step mean training loss of this thread's last fit_precond_train:
  * copies min(max, steps) values to out (may be NULL); *n = steps. */
 fit_status fit_precond_train_history(double *out, int max, int *n);

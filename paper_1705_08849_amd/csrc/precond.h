@@ -18,4 +18,10 @@ struct PrecondApply {
 // the object cannot serve this grid).  The caller deletes the adapter.
 PrecondApply* precond_apply_of(fit_precond* p, const fit_grid* g, double omega);
 
+// Solver-generated residual -> error pairs (fit_precond_harvest): e and r
+// hold npairs complex128 vectors of g back to back; *made receives how many
+// were written (fewer if the solve ends before the last snapshot).
+fit_status harvest_pairs(fit_grid* g, double omega, int port, int npairs, double tol, double* e,
+                         double* r, int* made, int* iterations);
+
 }  // namespace fit

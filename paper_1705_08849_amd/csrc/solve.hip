@@ -224,6 +224,8 @@ static fit_status gmres(Ctx& c, GmVecs<T>& V, int m, double tol_rel, int max_ite
   *done = kRunning;
   const int nblk_md = (int)((ne + 256 * kMdPer - 1) / (256 * kMdPer));
   int cur = 0;
+  double best_beta = beta;
+  int cycle = 0, best_cycle = 0;
   while (true) {
     if (!(beta > 0.0)) {
       *done = beta == 0.0 ? kConverged : kNan;
@@ -321,6 +323,15 @@ static fit_status gmres(Ctx& c, GmVecs<T>& V, int m, double tol_rel, int max_ite
     beta = std::sqrt(c.h_red->v[0]);
     if (beta <= target) {
       *done = kConverged;
+      break;
+    }
+    ++cycle;
+    if (beta < 0.5 * best_beta) {
+      best_beta = beta;
+      best_cycle = cycle;
+    } else if (c.gm_stall_cycles > 0 && cycle - best_cycle >= c.gm_stall_cycles) {
+      *done = kBreakdown;  // stalled: the caller falls back
+      c.last_reason = 9;
       break;
     }
   }
@@ -526,6 +537,17 @@ static fit_status cocg(Ctx& c, BiVecs<T>& V, double tol_rel, int max_iter, int c
     c.matvecs += c.h_cst->iter - last_iter;
     last_iter = c.h_cst->iter;
     if (c.h_cst->done != kRunning) break;
+    if constexpr (sizeof(T) == 8) {
+      // an iterate of the solve for the pair harvest (with the fused path x
+      // lags one step: still an iterate of the same Krylov sequence)
+      if (c.snap && c.snap_active && c.snap_n < c.snap_cap &&
+          c.h_cst->iter >= (c.snap_n + 1) * c.snap_stride) {
+        if ((ret = xform<T, double, XF_SCALE>(c, false, false, V.x, c.snap + c.snap_n * c.snap_ld,
+                                              c.inner_eta, false)) != FIT_OK)
+          break;
+        ++c.snap_n;
+      }
+    }
     if (c.h_cst->rr < 0.25 * best_rr) {
       best_rr = c.h_cst->rr;
       best_at = c.h_cst->iter;
@@ -936,6 +958,8 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
     int done = 0, it = 0;
     const int budget = o.max_iters - iters;
     if (budget <= 0) break;
+    c.inner_eta = eta;
+    c.snap_active = refin == 0 && rcur == r_init;
     const int hoff = std::min(iters, o.resid_history_len);
     if ((st = run_inner<T>(c, in, q, budget, o.check_every, rel, hist ? hist + hoff : nullptr,
                            o.resid_history_len - hoff, o.use_graph, pre, &done, &it)) != FIT_OK)
@@ -990,6 +1014,11 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
       rnorm = rn;
       break;
     }
+    if (done == kBreakdown && c.gm_stall_cycles > 0) {
+      result = FIT_E_BREAKDOWN;  // the learned preconditioner stalled: fall back
+      rnorm = rn;
+      break;
+    }
     if (done == kBreakdown && in.solver == FIT_BICGSTAB) ++breakdowns;
     if (rn / bnorm < 0.5 * best) {
       best = rn / bnorm;
@@ -1020,8 +1049,31 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
 
 }  // namespace
 
+namespace fit {
+// Iterates kept by a solve for the pair harvest (see Ctx::snap).
+struct SnapRequest {
+  double* buf;
+  int64_t ld;
+  int cap, stride;
+  int made = 0;
+};
+}  // namespace fit
+
+namespace {
+fit_status solve_impl(fit_grid* g, double omega, const void* source_dev, double tol,
+                      const fit_solve_opts* opts, void* x_dev, fit_solve_info* info,
+                      SnapRequest* snap);
+}  // namespace
+
 extern "C" fit_status fit_solve(fit_grid* g, double omega, const void* source_dev, double tol,
                                 const fit_solve_opts* opts, void* x_dev, fit_solve_info* info) {
+  return solve_impl(g, omega, source_dev, tol, opts, x_dev, info, nullptr);
+}
+
+namespace {
+fit_status solve_impl(fit_grid* g, double omega, const void* source_dev, double tol,
+                      const fit_solve_opts* opts, void* x_dev, fit_solve_info* info,
+                      SnapRequest* snap) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!g || !source_dev || !x_dev) {
     set_error("fit_solve: NULL argument");
@@ -1058,15 +1110,25 @@ extern "C" fit_status fit_solve(fit_grid* g, double omega, const void* source_de
   fit_status st = setup_ctx(c, g, omega, o.scaling == FIT_SCALE_SYM, s);
   if (st != FIT_OK) return st;
   c.diag = o.diag;
+  if (snap) {
+    c.snap = snap->buf;
+    c.snap_ld = snap->ld;
+    c.snap_cap = snap->cap;
+    c.snap_stride = std::max(1, snap->stride);
+  }
+  const bool learned = o.solver == FIT_FGMRES && o.precond != nullptr;
+  if (learned) c.gm_stall_cycles = 10;
 
   const int64_t ne = g->ne;
   const size_t v128 = align_up((size_t)ne * 16, 256);
   const bool mixed = o.precision == FIT_PREC_MIXED;
   // The mixed form reserves room for a complex128 inner solve as well, so a
   // fallback carves the same arena (b, r and the residual history stay put).
-  const size_t in_bytes = mixed ? std::max(inner_bytes<float>(ne, o.solver, o.restart),
-                                           inner_bytes<double>(ne, o.solver, o.restart))
-                                : inner_bytes<double>(ne, o.solver, o.restart);
+  size_t in_bytes = mixed ? std::max(inner_bytes<float>(ne, o.solver, o.restart),
+                                     inner_bytes<double>(ne, o.solver, o.restart))
+                          : inner_bytes<double>(ne, o.solver, o.restart);
+  // a learned FGMRES preconditioner can fall back to COCG in the same arena
+  if (learned) in_bytes = std::max(in_bytes, inner_bytes<double>(ne, FIT_COCG, o.restart));
   const size_t hist_bytes = align_up(sizeof(double) * (size_t)std::max(o.resid_history_len, 1), 256);
   if ((st = ensure_ws(g->ws, 2 * v128 + in_bytes + hist_bytes + 4096, g->device)) != FIT_OK) return st;
   Arena a{(char*)g->ws.ptr, 0, g->ws.bytes};
@@ -1140,7 +1202,35 @@ extern "C" fit_status fit_solve(fit_grid* g, double omega, const void* source_de
     inner_carve<double>(a, in, ne, o.solver, o.restart);
     result = refine<double>(c, in, b, bnorm, x, r, b, bnorm, tol, o, o.inner_tol, pre, hist, inf,
                             &relres, &iters);
+    if (learned && result != FIT_OK && result != FIT_E_NAN && iters < o.max_iters) {
+      // The learned preconditioner stalled: finish with the plain method
+      // (mass-preconditioned COCG, the symmetric scaling of eq. (e2t)) from
+      // the current x, judged by the same true FP64 residual.
+      inf.fell_back = 1;
+      c.gm_stall_cycles = 0;
+      c.sym = 1;
+      c.diag = FIT_DIAG_AUTO;
+      Arena a2{(char*)g->ws.ptr, 0, g->ws.bytes};
+      (void)a2.take<double>(v128);
+      (void)a2.take<double>(v128);
+      if (hist) (void)a2.take<double>(hist_bytes);
+      Inner<double> in2;
+      inner_carve<double>(a2, in2, ne, FIT_COCG, o.restart);
+      fit_solve_opts o2 = o;
+      o2.solver = FIT_COCG;
+      o2.max_iters = o.max_iters - iters;
+      const int hoff = std::min(iters, o.resid_history_len);
+      o2.resid_history_len = o.resid_history_len - hoff;
+      double* hist2 = (hist && o2.resid_history_len > 0) ? hist + hoff : nullptr;
+      if ((st = residual(c, x, b, r, nullptr, 0.0)) != FIT_OK) return st;
+      if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+      int it2 = 0;
+      result = refine<double>(c, in2, b, bnorm, x, r, r, std::sqrt(c.h_red->v[0]), tol, o2,
+                              o.inner_tol, nullptr, hist2, inf, &relres, &it2);
+      iters += it2;
+    }
   }
+  if (snap) snap->made = c.snap_n;
   if (pre && pre != &ident) delete pre;
   if (hist && o.resid_history) {
     const int n = std::min(o.resid_history_len, iters);
@@ -1161,6 +1251,85 @@ extern "C" fit_status fit_solve(fit_grid* g, double omega, const void* source_de
     set_error(std::string("fit_solve: ") + names[result] + " (relres " + std::to_string(relres) + ")");
   }
   return result;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Residual -> error pairs generated by the solver, for training the learned
+// preconditioner: x* from a COCG solve to tol, then a second identical solve
+// keeps its iterate x_k at npairs evenly spaced polls; e_k = x* - x_k and
+// r_k = A(omega) e_k (equal to b - A x_k up to rounding).
+// ---------------------------------------------------------------------------
+namespace fit {
+fit_status harvest_pairs(fit_grid* g, double omega, int port, int npairs, double tol, double* e,
+                         double* r, int* made, int* iterations) {
+  DeviceScope dev(g->device);
+  const int64_t ne = g->ne;
+  *made = 0;
+  std::vector<double> hsrc((size_t)2 * ne, 0.0);
+  const fit_port& q = (*g->host_ports)[port];
+  for (int k = q.k0; k < q.k1; ++k)
+    hsrc[2 * (3 * ((int64_t)q.i + (int64_t)g->view.nx * (q.j + (int64_t)g->view.ny * k)) + 2)] = 1.0;
+  double *src = nullptr, *xs = nullptr, *xt = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(src);
+    (void)hipFree(xs);
+    (void)hipFree(xt);
+  };
+  if (hipMalloc(&src, ne * 16) != hipSuccess || hipMalloc(&xs, ne * 16) != hipSuccess ||
+      hipMalloc(&xt, ne * 16) != hipSuccess) {
+    cleanup();
+    set_error("fit_precond_harvest: out of device memory");
+    return FIT_E_NOMEM;
+  }
+  fit_status st = FIT_OK;
+  if (hipMemcpy(src, hsrc.data(), ne * 16, hipMemcpyHostToDevice) != hipSuccess) st = FIT_E_DEVICE;
+  fit_solve_opts o{};
+  o.solver = FIT_COCG;
+  o.scaling = FIT_SCALE_SYM;
+  o.max_iters = 200000;
+  fit_solve_info i1{}, i2{};
+  if (st == FIT_OK) st = solve_impl(g, omega, src, tol, &o, xs, &i1, nullptr);
+  if (st == FIT_OK) {
+    // snapshots every `stride` iterations, strictly before convergence; the
+    // host polls (where snapshots are taken) at that spacing
+    const int stride = std::max(2, i1.iterations / (npairs + 1)) & ~1;
+    SnapRequest req{e, ne * 2, npairs, stride};
+    fit_solve_opts o2 = o;
+    o2.check_every = stride;
+    st = solve_impl(g, omega, src, tol, &o2, xt, &i2, &req);
+    *made = req.made;
+  }
+  if (iterations) *iterations = i1.iterations;
+  if (st == FIT_OK) {
+    Ctx c;
+    st = setup_ctx(c, g, omega, 0, nullptr);
+    for (int k = 0; k < *made && st == FIT_OK; ++k) {
+      double* ek = e + (int64_t)k * ne * 2;
+      double* rk = r + (int64_t)k * ne * 2;
+      // e_k = x* - x_k, r_k = A e_k
+      st = xform<double, double, XF_SCALE>(c, false, false, ek, ek, -1.0, false);
+      if (st == FIT_OK) st = xform<double, double, XF_AXPY>(c, false, false, xs, ek, 1.0, false);
+      OpMatvec<double> mv{ek, rk};
+      if (st == FIT_OK) st = launch_stencil<double, MODE_D>(g->view, tile_for(g, FIT_C128), omega, mv, nullptr);
+    }
+    if (st == FIT_OK && hipDeviceSynchronize() != hipSuccess) st = FIT_E_DEVICE;
+  }
+  cleanup();
+  return st;
+}
+}  // namespace fit
+
+extern "C" fit_status fit_precond_harvest(fit_grid* g, double omega, int port, int npairs, double tol,
+                                          void* e_dev, void* r_dev, int* made, int* iterations) {
+  if (!g || !e_dev || !r_dev || !made || npairs < 1 || port < 0 || port >= g->nports ||
+      !(omega > 0.0) || !std::isfinite(omega) || !(tol > 0.0) || !(tol < 1.0)) {
+    set_error("fit_precond_harvest: bad argument (NULL, npairs < 1, port outside the grid's "
+              "ports, omega <= 0 or tol outside (0, 1))");
+    return FIT_E_INVALID;
+  }
+  return harvest_pairs(g, omega, port, npairs, tol, (double*)e_dev, (double*)r_dev, made,
+                       iterations);
 }
 
 // ---------------------------------------------------------------------------

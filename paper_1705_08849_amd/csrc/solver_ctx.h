@@ -39,6 +39,17 @@ struct Ctx {
   int max_blocks;
   double bytes = 0.0;  // algorithmic bytes launched
   int matvecs = 0;
+  // iterate snapshots of the first inner COCG solve (training pairs of the
+  // learned preconditioner): every snap_stride iterations, eta * x of the
+  // inner solve goes to snap + k * snap_ld, k < snap_cap
+  double* snap = nullptr;
+  int64_t snap_ld = 0;
+  int snap_cap = 0, snap_stride = 0, snap_n = 0;
+  bool snap_active = false;
+  double inner_eta = 1.0;  // scale of the current inner solve's rhs (x_outer += eta d)
+  // FGMRES with a learned preconditioner: stop as stalled when the restart
+  // residual has not halved within this many cycles (0: never)
+  int gm_stall_cycles = 0;
   int last_reason = 0;   // breakdown test of the last inner BiCGStab
   double last_rr = 0.0;  // its final recursive ||r||^2 (unit initial norm)
   TileShape tile128, tile64;

@@ -141,6 +141,9 @@ _SIGS = [
     ("fit_precond_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
                                         C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
     ("fit_precond_train_history", C.c_int, [C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int)]),
+    ("fit_precond_harvest", C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_double,
+                                      C.c_void_p, C.c_void_p, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]),
     ("fit_tile_set", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]),
     ("fit_autotune", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p,
                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -400,9 +403,24 @@ class Precond:
 
     @staticmethod
     def _cfg(base_channels=16, steps=0, batch=0, crop=0, seed=0, lr=0.0, weight_decay=0.0,
-             stream=None):
-        return PrecondCfg(base_channels, steps, batch, crop, 0, seed, lr, weight_decay,
-                          _stream_ptr(stream))
+             stream=None, pairs_per_system=0):
+        return PrecondCfg(base_channels, steps, batch, crop, pairs_per_system, seed, lr,
+                          weight_decay, _stream_ptr(stream))
+
+    @staticmethod
+    def harvest(grid: "Grid", omega: float, port: int = 0, npairs: int = 8, tol: float = 1e-8):
+        """``fit_precond_harvest``: solver-generated pairs (e, r), each a
+        complex128 tensor of shape (made, n_e); returns (e, r, iterations)."""
+        torch = _torch()
+        n = grid.n_edges
+        e = torch.empty(npairs * n, dtype=torch.complex128, device=f"cuda:{grid.device}")
+        r = torch.empty_like(e)
+        made, iters = C.c_int(), C.c_int()
+        check(lib().fit_precond_harvest(grid.h, float(omega), port, npairs, float(tol), _dptr(e),
+                                        _dptr(r), C.byref(made), C.byref(iters)),
+              "fit_precond_harvest")
+        m = made.value
+        return e[: m * n].view(m, n), r[: m * n].view(m, n), iters.value
 
     @classmethod
     def create(cls, base_channels: int = 16, seed: int = 0, device: int = 0):

@@ -184,3 +184,59 @@ def test_full_size_family_device():
     print(f"192x192x96 c=16 application vs oracle: rel err {rel:.3e}")
     # the small-grid bar: fp32 accumulation order can flip a stored bf16 value
     assert rel <= 1e-2
+
+
+def test_solver_generated_pairs_are_residual_error_pairs():
+    """fit_precond_harvest: e_k = x* - x_k from COCG iterates of the port
+    excitation and r_k = A e_k, checked by the oracle (r_k against its own
+    operator applied to e_k, x* against its residual), with the errors taken
+    strictly before convergence (every pair nonzero)."""
+    dev = D.layered_device(24, 20, 12, n_layers=3, n_strips=2, n_ports=2, seed=21)
+    g = fit.Grid(dev)
+    om = 2 * np.pi * 9e9
+    e, r, iters = fit.Precond.harvest(g, om, port=1, npairs=6, tol=1e-9)
+    assert e.shape[0] == 6 and iters > 0
+    eh, rh = e.cpu().numpy(), r.cpu().numpy()
+    src = D.port_source(dev, 1)
+    b = np.zeros(dev.n_edges, complex)
+    b[O.free_edges(dev)] = O.rhs(dev, om, src)
+    for k in range(6):
+        ref = O.matvec(dev, om, eh[k])
+        assert np.linalg.norm(rh[k] - ref) <= 1e-12 * np.linalg.norm(ref)
+        assert np.linalg.norm(eh[k]) > 0 and np.all(eh[k][~O.free_edges(dev)] == 0)
+        # x_k = x* - e_k is an iterate: b - A x_k = r(x*) + r_k with r(x*) <= 1e-9 |b|
+        assert np.linalg.norm(rh[k]) > 1e-6 * np.linalg.norm(b)
+    # x* itself: the last error plus the iterate it came from is a solution
+    x, _ = g.solve(om, _cuda(src), tol=1e-9, solver="cocg")
+    assert O.relative_residual(dev, om, src, x.cpu().numpy()) <= 1e-9
+
+
+def test_training_on_solver_generated_pairs_lowers_the_loss():
+    devs = [D.layered_device(28, 24, 16, n_layers=3, n_strips=2, n_ports=1, seed=s)
+            for s in (1000, 1001)]
+    grids = [fit.Grid(d) for d in devs]
+    pre = fit.Precond.train(grids, [2 * np.pi * 5e9, 2 * np.pi * 20e9], base_channels=8,
+                            steps=120, batch=4, crop=16, seed=5, pairs_per_system=4)
+    h = fit.Precond.train_history()
+    assert len(h) == 120 and np.all(np.isfinite(h))
+    assert h[-20:].mean() < h[:10].mean()
+
+
+def test_learned_fgmres_falls_back_to_cocg_on_stagnation():
+    """A network that does not precondition (seeded random weights) makes
+    FGMRES(30) stall; after 10 restart cycles without halving the true
+    residual the solve continues with the mass-preconditioned COCG from the
+    current iterate and meets the tolerance, reporting the fallback."""
+    dev = D.layered_device(24, 20, 12, n_layers=3, n_strips=2, n_ports=2, seed=21)
+    g = fit.Grid(dev)
+    pre = fit.Precond.create(base_channels=8, seed=1)
+    om = 2 * np.pi * 9e9
+    src = D.port_source(dev, 0)
+    x, info = g.solve(om, _cuda(src), tol=1e-8, solver="fgmres", precond=pre, max_iters=20000)
+    rr = O.relative_residual(dev, om, src, x.cpu().numpy())
+    print(f"fgmres+net: iters {info['iterations']} fell back {info['fell_back']} relres {rr:.2e}")
+    assert info["status_name"] == "FIT_OK" and info["fell_back"] == 1
+    assert rr <= 1e-8 and abs(rr - info["true_relres"]) <= 1e-9
+    # the learned stage spent at most the stall window before handing over
+    _, plain = g.solve(om, _cuda(src), tol=1e-8, solver="cocg")
+    assert info["iterations"] <= plain["iterations"] + 30 * 12
