@@ -73,7 +73,8 @@ def bench_tile(fit, g, dev, omega, args):
             if (e["nx"], e["ny"], e["nz"], e["dtype"]) == (nx, ny, nz, fit.C128):
                 fit.tune_load(TUNE_FILE)
                 return (e["tx"], e["ty"], e["zc"])
-    tile, _ = g.autotune("c128", "none", omega, reps=20)
+    # tuned on the solver's own iteration (fused COCG step + update kernel)
+    tile, _ = g.autotune_solver(omega, iters=1000)
     if args.save_tune:
         fit.tune_save(TUNE_FILE)
     return tile
@@ -173,7 +174,8 @@ def sweep_row(fit, D, np, torch, with_cpu):
     sd = D.sweep_devices(seeds=[40], shapes=[(64, 64, 32)])[0]
     g = fit.Grid(sd)
     oms = D.log_spaced_omegas(16, 5e9, 40e9)
-    g.autotune("c128", "none", float(oms[8]), reps=3)
+    g.autotune_solver(float(oms[8]), iters=40)
+    batch, _ = g.autotune_sweep(oms, iters=40)
     src = torch.from_numpy(D.port_source(sd, 0)).to("cuda:0")
     fit.sweep([g], oms[:2], [src[None, :]], tol=1e-8)  # warm-up
     torch.cuda.synchronize()
@@ -189,7 +191,8 @@ def sweep_row(fit, D, np, torch, with_cpu):
     iters = [i["iterations"] for i in infos]
     row = {"workload": "64x64x32-cell sweep-family device (seed 40), 16 log-spaced frequencies "
                        "5-40 GHz, one port excitation, COCG fp64 to 1e-8",
-           "status": fit.STATUS_NAMES[st], "points": 16, "batched_points_per_s": round(16 / tb, 3),
+           "status": fit.STATUS_NAMES[st], "points": 16, "systems_per_batch": batch,
+           "batched_points_per_s": round(16 / tb, 3),
            "sequential_points_per_s": round(16 / ts, 3), "speedup": round(ts / tb, 3),
            "iterations": [min(iters), max(iters)]}
     if with_cpu:
@@ -304,6 +307,8 @@ def interconnect_row(fit, D, np, torch, mean_us):
     n_nodes, n_cells = nx * ny * nz, dev.ncx * dev.ncy * dev.ncz
     om = 2 * np.pi * 10e9
     g = fit.Grid(dev)
+    if os.path.exists(TUNE_FILE):
+        fit.tune_load(TUNE_FILE)  # the committed table's tile for this grid, if it has one
     xv = torch.randn(dev.n_edges, dtype=torch.complex128, device="cuda:0")
     yv = torch.empty_like(xv)
     mv_us = mean_us(lambda: g.matvec(om, xv, yv, scaling="none"))
@@ -416,6 +421,9 @@ def main():
                     help="autotune the bench grid instead of reading the committed tile table")
     ap.add_argument("--save-tune", action="store_true",
                     help="with --autotune: write the tile table to the committed file")
+    ap.add_argument("--tune-interconnect", action="store_true",
+                    help="tune the 256x256x128 interconnect grid's tile on the COCG iteration and "
+                         "add it to the committed tile table")
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the secondary rows (batched sweep, learned preconditioner)")
     ap.add_argument("--row", choices=["sweep", "precond", "interconnect"],
@@ -438,6 +446,21 @@ def main():
         sys.exit(2)
     if args.counters:
         counter_sample(args)
+        return
+    if args.tune_interconnect:
+        import numpy as np
+
+        import torch
+
+        from paper_1705_08849_amd import devices as D
+        from paper_1705_08849_amd import fit
+        torch.cuda.init()
+        if os.path.exists(TUNE_FILE):
+            fit.tune_load(TUNE_FILE)
+        g = fit.Grid(D.interconnect_256(3))
+        tile, us = g.autotune_solver(2 * np.pi * 10e9, iters=400)
+        fit.tune_save(TUNE_FILE)
+        print(json.dumps({"interconnect_tile": tile, "us_per_iteration": us}), flush=True)
         return
     if args.row:
         import numpy as np

@@ -347,6 +347,31 @@ fit_status fit_tile_set(const struct fit_grid *g, int dtype, int tx, int ty, int
 fit_status fit_autotune(const struct fit_grid *g, int dtype, int scaling, double omega, int reps,
                         void *stream, int32_t *tx, int32_t *ty, int32_t *zc, double *best_us);
 
+/* Time every compiled (TX, TY) with a range of ZC on the solver's own
+ * iteration instead of the plain operator: the complex128 COCG with the
+ * symmetric scaling (fused operator step and update kernel, captured graphs)
+ * at omega, from the difference of two solves capped at iters and 2 iters
+ * iterations (which removes set-up and graph capture), with a source of 1 A
+ * on every free edge; record the fastest for complex128 and report it with
+ * its time per iteration.  Same candidate order and 2 % rule as fit_autotune.
+ * Synchronous; allocates three work vectors. */
+fit_status fit_autotune_solver(struct fit_grid *g, double omega, int iters, void *stream,
+                               int32_t *tx, int32_t *ty, int32_t *zc, double *best_us_per_iter);
+
+/* Systems that fit_sweep advances together in one batch (one operator launch
+ * over all of them per iteration), process-wide; 1..64 (default 64).  The
+ * per-system results do not depend on it. */
+fit_status fit_sweep_set_batch(int systems);
+
+/* Choose fit_sweep's systems per batch for grids like g: time `iters` COCG
+ * iterations (difference of runs of iters and 2 iters) of batches of 4, 8,
+ * 16, 32 and 64 systems (frequencies taken from omegas, at most nomega), one
+ * source of 1 A on every free edge, and keep the batch size with the most
+ * system-iterations per second (a larger one must win by more than 2 %).
+ * Sets the process-wide batch size; reports it and its rate.  Synchronous. */
+fit_status fit_autotune_sweep(struct fit_grid *g, const double *omegas, int nomega, int iters,
+                              void *stream, int32_t *best_batch, double *best_rate);
+
 /* Write / read the tile table as JSON ({"entries": [{"nx":..,"ny":..,"nz":..,
  * "dtype":..,"tx":..,"ty":..,"zc":..,"us":..}, ...], "arch": "gfx950"}). */
 fit_status fit_tune_save(const char *path);

@@ -19,6 +19,7 @@
 // (x += ||r|| d, true residual recomputed in complex128) and finishes any
 // system whose complex64 refinement stalls in complex128.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -43,6 +44,9 @@ using namespace fit;
 namespace {
 
 constexpr int kMaxBatch = 64;
+// systems advanced together per batch (at most kMaxBatch); set by
+// fit_sweep_set_batch or fit_autotune_sweep, process-wide
+std::atomic<int> g_sweep_batch{kMaxBatch};
 
 // One system of the sweep.
 struct Sys {
@@ -519,7 +523,8 @@ extern "C" fit_status fit_sweep(fit_grid* const* grids, int ngrids, const double
   for (int i = 0; i < nsys;) {
     size_t used = 0;
     int j = i;
-    while (j < nsys && j - i < kMaxBatch) {
+    const int cap = std::max(1, std::min<int>(kMaxBatch, g_sweep_batch.load()));
+    while (j < nsys && j - i < cap) {
       const size_t need = sys_bytes(all[j].g, own_x, all[j].max_blocks);
       if (j > i && used + need > budget) break;
       used += need;
@@ -676,4 +681,110 @@ extern "C" fit_status fit_sweep(fit_grid* const* grids, int ngrids, const double
               " systems did not reach tol");
   }
   return result;
+}
+
+// ---------------------------------------------------------------------------
+// Systems per batch: a process-wide setting and its autotuner.
+// ---------------------------------------------------------------------------
+extern "C" fit_status fit_sweep_set_batch(int systems) {
+  if (systems < 1 || systems > kMaxBatch) {
+    set_error("fit_sweep_set_batch: systems must be in [1, 64]");
+    return FIT_E_INVALID;
+  }
+  g_sweep_batch.store(systems);
+  return FIT_OK;
+}
+
+namespace {
+__global__ void mask_to_source_kernel(const uint8_t* mask, int64_t ne, int nrep, double* src) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne * nrep;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    src[2 * e] = mask[e % ne] ? 1.0 : 0.0;
+    src[2 * e + 1] = 0.0;
+  }
+}
+}  // namespace
+
+extern "C" fit_status fit_autotune_sweep(fit_grid* g, const double* omegas, int nomega, int iters,
+                                         void* stream, int32_t* best_batch, double* best_rate) {
+  if (!g || !omegas || nomega < 1 || nomega > 4096 || iters < 2) {
+    set_error("fit_autotune_sweep: bad argument (NULL, nomega outside [1, 4096] or iters < 2)");
+    return FIT_E_INVALID;
+  }
+  for (int f = 0; f < nomega; ++f)
+    if (!(omegas[f] > 0.0) || !std::isfinite(omegas[f])) {
+      set_error("fit_autotune_sweep: omegas must be finite and > 0");
+      return FIT_E_INVALID;
+    }
+  DeviceScope dev(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  // one right-hand side: 1 A on every free edge (the tuner times iterations,
+  // it never converges at the tolerance below)
+  uint8_t* mask = nullptr;
+  double* src = nullptr;
+  FIT_HIP(hipMalloc(&mask, g->ne));
+  hipError_t he = hipMalloc(&src, (size_t)g->ne * 16);
+  if (he != hipSuccess) {
+    (void)hipFree(mask);
+    return hip_fail(he, "hipMalloc(autotune_sweep)");
+  }
+  fit_status st = fit_edge_mask(g, mask, s);
+  if (st == FIT_OK) {
+    hipLaunchKernelGGL(mask_to_source_kernel, dim3(1024), dim3(256), 0, s, mask, g->ne, 1, src);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) st = FIT_E_DEVICE;
+  }
+  const int saved = g_sweep_batch.load();
+  int best_b = saved;
+  double best = -1.0;
+  fit_grid* grids[1] = {g};
+  const void* srcs[1] = {src};
+  auto run = [&](int nf, int cap, double* secs, int64_t* sys_iters) -> fit_status {
+    fit_solve_opts o{};
+    o.solver = FIT_COCG;
+    o.precision = FIT_PREC_FP64;
+    o.max_iters = cap;
+    o.check_every = iters;
+    o.use_graph = 1;
+    o.stream = stream;
+    std::vector<fit_solve_info> infos((size_t)nf);
+    const auto t0 = std::chrono::steady_clock::now();
+    const fit_status e = fit_sweep(grids, 1, omegas, nf, srcs, 1, 1e-15, &o, nullptr, nullptr,
+                                   infos.data());
+    *secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *sys_iters = 0;
+    for (auto& i : infos) *sys_iters += i.iterations;
+    return (e == FIT_OK || e == FIT_E_NOT_CONVERGED || e == FIT_E_BREAKDOWN) ? FIT_OK : e;
+  };
+  if (st == FIT_OK) {  // warm-up: first-use allocations stay out of the timed pairs
+    double w = 0.0;
+    int64_t wi = 0;
+    g_sweep_batch.store(4);
+    st = run(std::min(nomega, 4), iters, &w, &wi);
+  }
+  for (int b : {4, 8, 16, 32, 64}) {
+    if (st != FIT_OK) break;
+    if (b > nomega && b != 4) break;
+    g_sweep_batch.store(b);
+    const int nf = std::min(nomega, b);
+    double secs[2] = {0.0, 0.0};
+    int64_t its[2] = {0, 0};
+    for (int rep = 0; rep < 2 && st == FIT_OK; ++rep)
+      st = run(nf, rep == 0 ? iters : 2 * iters, &secs[rep], &its[rep]);
+    if (st != FIT_OK) break;
+    if (its[1] <= its[0]) continue;
+    // system-iterations per second of the iteration itself (the difference
+    // of the two runs removes set-up and graph capture)
+    const double rate = (double)(its[1] - its[0]) / std::max(secs[1] - secs[0], 1e-9);
+    if (rate > 1.02 * best) {
+      best = rate;
+      best_b = b;
+    }
+  }
+  (void)hipFree(mask);
+  (void)hipFree(src);
+  g_sweep_batch.store(st == FIT_OK ? best_b : saved);
+  if (st != FIT_OK) return st;
+  if (best_batch) *best_batch = best_b;
+  if (best_rate) *best_rate = best;
+  return FIT_OK;
 }

@@ -1,6 +1,8 @@
 // Tile-shape table, defaults and the on-device autotuner.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -233,5 +235,96 @@ extern "C" fit_status fit_tune_load(const char* path) {
     pos = end;
   }
   (void)loaded;
+  return FIT_OK;
+}
+
+// Tile autotuning of the solver's own iteration: for every compiled shape and
+// z-chunk, the time of the mass-preconditioned COCG iteration (fused operator
+// step and update kernel) from the difference of two capped solves.
+extern "C" fit_status fit_autotune_solver(fit_grid* g, double omega, int iters, void* stream,
+                                          int32_t* tx, int32_t* ty, int32_t* zc,
+                                          double* best_us_per_iter) {
+  if (!g || !(omega > 0.0) || !std::isfinite(omega) || iters < 2) {
+    set_error("fit_autotune_solver: bad argument (NULL grid, omega <= 0 or iters < 2)");
+    return FIT_E_INVALID;
+  }
+  DeviceScope dev(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* mask = nullptr;
+  double *src = nullptr, *x = nullptr;
+  FIT_HIP(hipMalloc(&mask, g->ne));
+  fit_status st = FIT_OK;
+  if (hipMalloc(&src, (size_t)g->ne * 16) != hipSuccess || hipMalloc(&x, (size_t)g->ne * 16) != hipSuccess)
+    st = FIT_E_NOMEM;
+  if (st == FIT_OK) st = fit_edge_mask(g, mask, s);
+  if (st == FIT_OK) {
+    // 1 A on every free edge: a source that never converges within the caps
+    std::vector<uint8_t> hm((size_t)g->ne);
+    std::vector<double> hs((size_t)g->ne * 2, 0.0);
+    if (hipMemcpy(hm.data(), mask, g->ne, hipMemcpyDeviceToHost) != hipSuccess) st = FIT_E_DEVICE;
+    for (int64_t e = 0; e < g->ne && st == FIT_OK; ++e) hs[2 * e] = hm[e] ? 1.0 : 0.0;
+    if (st == FIT_OK && hipMemcpy(src, hs.data(), hs.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      st = FIT_E_DEVICE;
+  }
+  const TileShape saved = tile_for(g, FIT_C128);
+  // the first solve on a grid allocates its workspace: keep that out of the
+  // timed pairs
+  auto run = [&](int cap, double* secs, int* its) -> fit_status {
+    fit_solve_opts o{};
+    o.solver = FIT_COCG;
+    o.scaling = FIT_SCALE_SYM;
+    o.max_iters = cap;
+    o.check_every = iters;
+    o.use_graph = 1;
+    o.stream = stream;
+    fit_solve_info info{};
+    const auto t0 = std::chrono::steady_clock::now();
+    const fit_status e = fit_solve(g, omega, src, 1e-15, &o, x, &info);
+    *secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *its = info.iterations;
+    return (e == FIT_OK || e == FIT_E_NOT_CONVERGED || e == FIT_E_BREAKDOWN) ? FIT_OK : e;
+  };
+  if (st == FIT_OK) {
+    double w = 0.0;
+    int wi = 0;
+    st = run(iters, &w, &wi);
+  }
+  const int zcs[] = {4, 8, 12, 14, 16, 24, 32, 48, 64, 96, 128};
+  const TileShape shapes[] = {{64, 8, 0}, {48, 8, 0}, {32, 8, 0}, {32, 16, 0}};
+  TileShape best = saved;
+  double best_t = 1e300;
+  for (TileShape base : shapes) {
+    for (int z : zcs) {
+      if (st != FIT_OK) break;
+      if ((z > g->view.nz && z != zcs[0]) || z > kMaxZChunk) continue;
+      TileShape t = base;
+      t.zc = z;
+      record_tile(g->view, FIT_C128, t, 0.0);
+      double secs[2] = {0.0, 0.0};
+      int its[2] = {0, 0};
+      for (int rep = 0; rep < 2 && st == FIT_OK; ++rep)
+        st = run(rep == 0 ? iters : 2 * iters, &secs[rep], &its[rep]);
+      // per iteration from the difference of the two runs (set-up and the
+      // solve's own overheads cancel); a run that stopped early is skipped
+      if (st != FIT_OK || its[1] <= its[0]) continue;
+      const double us = 1e6 * (secs[1] - secs[0]) / (its[1] - its[0]);
+      if (const char* v = std::getenv("FIT_VERBOSE"); v && *v && *v != '0')
+        std::fprintf(stderr, "[fit] autotune_solver %dx%d zc %d: %.2f us per iteration\n", t.tx, t.ty,
+                     t.zc, us);
+      if (us < 0.98 * best_t) {
+        best_t = us;
+        best = t;
+      }
+    }
+  }
+  (void)hipFree(mask);
+  (void)hipFree(src);
+  (void)hipFree(x);
+  record_tile(g->view, FIT_C128, st == FIT_OK ? best : saved, st == FIT_OK ? best_t : 0.0);
+  if (st != FIT_OK) return st;
+  if (tx) *tx = best.tx;
+  if (ty) *ty = best.ty;
+  if (zc) *zc = best.zc;
+  if (best_us_per_iter) *best_us_per_iter = best_t;
   return FIT_OK;
 }

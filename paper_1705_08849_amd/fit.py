@@ -145,6 +145,12 @@ _SIGS = [
                                       C.c_void_p, C.c_void_p, C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]),
     ("fit_tile_set", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]),
+    ("fit_autotune_solver", C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_void_p,
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    ("fit_sweep_set_batch", C.c_int, [C.c_int]),
+    ("fit_autotune_sweep", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_int,
+                                     C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("fit_autotune", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p,
                                C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                C.POINTER(C.c_double)]),
@@ -263,6 +269,24 @@ class Grid:
                                  C.byref(ty), C.byref(zc), C.byref(us)), "fit_autotune")
         return (tx.value, ty.value, zc.value), us.value
 
+    def autotune_solver(self, omega: float, iters: int = 200, stream=None):
+        """``fit_autotune_solver``: tile tuned on the COCG iteration itself;
+        returns ((tx, ty, zc), microseconds per iteration)."""
+        tx, ty, zc, us = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        check(lib().fit_autotune_solver(self.h, float(omega), iters, _stream_ptr(stream),
+                                        C.byref(tx), C.byref(ty), C.byref(zc), C.byref(us)),
+              "fit_autotune_solver")
+        return (tx.value, ty.value, zc.value), us.value
+
+    def autotune_sweep(self, omegas: Sequence[float], iters: int = 100, stream=None):
+        """``fit_autotune_sweep``: systems per batch for sweeps on grids like
+        this one; returns (batch, system-iterations per second)."""
+        om = (C.c_double * len(omegas))(*[float(o) for o in omegas])
+        b, rate = C.c_int32(), C.c_double()
+        check(lib().fit_autotune_sweep(self.h, om, len(omegas), iters, _stream_ptr(stream),
+                                       C.byref(b), C.byref(rate)), "fit_autotune_sweep")
+        return b.value, rate.value
+
     # -- debug exports ------------------------------------------------------
     def edge_mask(self, stream=None):
         torch = _torch()
@@ -341,6 +365,11 @@ class Grid:
               "fit_port_voltages_noalloc" if noalloc else "fit_port_voltages")
         a = np.frombuffer(out, dtype=np.float64)[: 2 * n * nvec].copy()
         return a.view(np.complex128).reshape(nvec, n)
+
+
+def sweep_set_batch(systems: int):
+    """``fit_sweep_set_batch``: systems per batch of ``sweep`` (1..64)."""
+    check(lib().fit_sweep_set_batch(int(systems)), "fit_sweep_set_batch")
 
 
 def port_network(zl, z0: float = 50.0):

@@ -173,3 +173,40 @@ def test_sweep_more_than_one_batch_and_graph_equals_eager():
             assert rr <= 1e-8, (f, r, rr)
             np.testing.assert_allclose(out[True][2][f, r], O.port_voltages(dev, xh[f, r]),
                                        rtol=1e-12, atol=1e-14 * np.abs(xh[f, r]).max())
+
+
+def test_batch_size_changes_no_result_and_the_sweep_tuner_picks_one():
+    """Systems per batch (fit_sweep_set_batch / fit_autotune_sweep) only
+    changes how systems share launches: fields and iteration counts are bit
+    for bit those of any other batch size."""
+    dev, _ = _devs()
+    g = fit.Grid(dev)
+    omegas = 2 * np.pi * np.geomspace(2e9, 30e9, 9)
+    src = _cuda(D.port_source(dev, 0)[None, :])
+    out = []
+    try:
+        for b in (4, 64):
+            fit.sweep_set_batch(b)
+            x = torch.empty(len(omegas) * dev.n_edges, dtype=torch.complex128, device="cuda:0")
+            st, pv, infos = fit.sweep([g], omegas, [src], tol=1e-8, xs=[x])
+            assert st == fit.OK
+            out.append((x, [i["iterations"] for i in infos]))
+        assert torch.equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+        b, rate = g.autotune_sweep(omegas, iters=20)
+        assert b in (4, 8, 16, 32, 64) and rate > 0
+    finally:
+        fit.sweep_set_batch(64)
+
+
+def test_solver_tile_autotuner():
+    """fit_autotune_solver times the COCG iteration for every compiled tile
+    and records the fastest; a solve afterwards runs with it and still meets
+    the tolerance."""
+    dev, _ = _devs()
+    g = fit.Grid(dev)
+    om = 2 * np.pi * 9e9
+    (tx, ty, zc), us = g.autotune_solver(om, iters=20)
+    assert (tx, ty) in ((64, 8), (48, 8), (32, 8), (32, 16)) and 1 <= zc <= 128 and us > 0
+    src = D.port_source(dev, 0)
+    x, info = g.solve(om, _cuda(src), tol=1e-8, solver="cocg")
+    assert O.relative_residual(dev, om, src, x.cpu().numpy()) <= 1e-8
