@@ -425,7 +425,8 @@ def main():
                     help="tune the 256x256x128 interconnect grid's tile on the COCG iteration and "
                          "add it to the committed tile table")
     ap.add_argument("--no-rows", action="store_true",
-                    help="skip the secondary rows (batched sweep, learned preconditioner)")
+                    help="skip the secondary rows (256x256x128 interconnect, batched sweep, learned "
+                         "preconditioner): only the bench grid runs")
     ap.add_argument("--row", choices=["sweep", "precond", "interconnect"],
                     help="run only this secondary row and print it as one JSON line")
     ap.add_argument("--counters", action="store_true",
@@ -594,13 +595,13 @@ def main():
         out["cpu_baseline"] = cpu_baseline(dev, omega, src_np, iters)
     # the plain operator's bandwidth on the largest single-GPU grid (its
     # working set exceeds the last-level cache), with the fused COCG step and
-    # one solve there
+    # one solve there; --no-rows keeps only the bench grid (profiled runs)
     del g, x
     torch.cuda.empty_cache()
-    ic = interconnect_row(fit, D, np, torch, mean_us)
-    out["matvec_128"] = out["matvec"]
-    out["matvec"] = dict(ic["matvec"], grid="256x256x128 cells (835 MB per application)")
     if not args.no_rows:
+        ic = interconnect_row(fit, D, np, torch, mean_us)
+        out["matvec_128"] = out["matvec"]
+        out["matvec"] = dict(ic["matvec"], grid="256x256x128 cells (835 MB per application)")
         out["rows"] = {"interconnect": ic,
                        "sweep": sweep_row(fit, D, np, torch, not args.no_cpu_baseline),
                        "precond": precond_row(fit, D, np, torch, not args.no_cpu_baseline)}
