@@ -80,14 +80,18 @@ typedef enum { FIT_SCALE_NONE = 0, FIT_SCALE_SYM = 1, FIT_SCALE_FACT = 2 } fit_s
  * application per iteration; FIT_TFQMR is the transpose-free QMR method of
  * the same comparison (Freund), two operator applications per iteration,
  * stopping on its residual bound tau sqrt(m + 1) before the true residual is
- * checked.  Both run on the internal operator (S A S with FIT_SCALE_SYM). */
+ * checked; FIT_CGS is conjugate gradients squared (Sonneveld), also two
+ * operator applications per iteration.  TFQMR and CGS use the dense shadow
+ * vector of BiCGStab.  All three run on the internal operator (S A S with
+ * FIT_SCALE_SYM). */
 typedef enum {
   FIT_BICGSTAB = 0,
   FIT_GMRES = 1,
   FIT_FGMRES = 2,
   FIT_COCG = 3,
   FIT_COCR = 4,
-  FIT_TFQMR = 5
+  FIT_TFQMR = 5,
+  FIT_CGS = 6
 } fit_solver;
 
 /* FIT_PREC_FP64:  complex128 operator and Krylov vectors throughout.
@@ -367,7 +371,8 @@ fit_status fit_sweep_set_batch(int systems);
  * iterations (difference of runs of iters and 2 iters) of batches of 4, 8,
  * 16, 32 and 64 systems (frequencies taken from omegas, at most nomega), one
  * source of 1 A on every free edge, and keep the batch size with the most
- * system-iterations per second (a larger one must win by more than 2 %).
+ * system-iterations per second, candidates from the largest down (a smaller
+ * one must win by more than 2 %: fewer batches leave fewer serial tails).
  * Sets the process-wide batch size; reports it and its rate.  Synchronous. */
 fit_status fit_autotune_sweep(struct fit_grid *g, const double *omegas, int nomega, int iters,
                               void *stream, int32_t *best_batch, double *best_rate);

@@ -561,6 +561,44 @@ def tfqmr(a, b, rhat, tol=1e-8, maxiter=100000, history=False):
     return x, it, rr
 
 
+def cgs(a, b, rhat, tol=1e-8, maxiter=100000, history=False):
+    """Conjugate gradients squared (Sonneveld, 1989) with conjugated inner
+    products against the shadow vector ``rhat`` (one of the methods of the
+    paper's comparison, Sec. IV): per iteration rho = <rhat, r>, beta =
+    rho/rho_old (0 at the start), u = r + beta q, p = u + beta (q + beta p),
+    alpha = rho/<rhat, A p>, q = u - alpha A p, x += alpha (u + q),
+    r -= alpha A (u + q).  Stops when the recursive ``||r|| <= tol ||b||``.
+    Returns ``(x, iterations, relres)`` and, with ``history``, the recursive
+    relative residual after every iteration."""
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = np.zeros_like(b)
+    q = np.zeros_like(b)
+    rho = np.vdot(rhat, r)
+    beta = 0.0
+    hist = []
+    it = 0
+    while it < maxiter and np.linalg.norm(r) > tol * nb:
+        it += 1
+        u = r + beta * q
+        p = u + beta * (q + beta * p)
+        v = a @ p
+        alpha = rho / np.vdot(rhat, v)
+        q = u - alpha * v
+        w = u + q
+        x = x + alpha * w
+        r = r - alpha * (a @ w)
+        hist.append(np.linalg.norm(r) / nb)
+        rho_new = np.vdot(rhat, r)
+        beta = rho_new / rho
+        rho = rho_new
+    rr = float(np.linalg.norm(b - a @ x) / nb)
+    if history:
+        return x, it, rr, np.array(hist)
+    return x, it, rr
+
+
 def gmres(a, b, restart=30, tol=1e-8, maxiter=100000, precond=None, x0=None):
     """Restarted GMRES(m) with classical Gram-Schmidt applied twice and
     Givens rotations; with ``precond`` it is flexible GMRES (right

@@ -1,7 +1,8 @@
-// The two further Krylov methods of the paper's solver comparison (Sec. IV):
-// the conjugate residual method in its complex symmetric form (COCR:
-// Sogabe & Zhang 2007, CR recurrences with the unconjugated bilinear form)
-// and the transpose-free QMR method (TFQMR: Freund 1993).  Both run on the
+// Further Krylov methods of the paper's solver comparison (Sec. IV): the
+// conjugate residual method in its complex symmetric form (COCR: Sogabe &
+// Zhang 2007, CR recurrences with the unconjugated bilinear form), the
+// transpose-free QMR method (TFQMR: Freund 1993) and conjugate gradients
+// squared (CGS: Sonneveld 1989).  Both run on the
 // internal operator of the solve (S A S with the symmetric scaling of
 // eq. (e2t)) with device-resident scalars, like BiCGStab and COCG: each
 // reduction ends in a one-block finish kernel that performs the scalar step,
@@ -341,6 +342,96 @@ __global__ void __launch_bounds__(256)
        e += (int64_t)gridDim.x * blockDim.x)
     stc(v, e, ldc(au0, e) + be * (ldc(au1, e) + be * ldc(v, e)));
 }
+
+// ===========================================================================
+// CGS (Sonneveld 1989) on A x = r0 from x = 0, conjugated inner products with
+// the shadow vector rh:
+//   rho = <rh, r>; beta = rho / rho_old (0 at the start, with p = q = 0);
+//   u = r + beta q; p = u + beta (q + beta p); v = A p;
+//   alpha = rho / <rh, v>; q = u - alpha v; w = u + q;
+//   x += alpha w; r -= alpha A w.
+// Scalars in TqState (rho, alpha, beta, rr, iteration count, stop code).
+// ===========================================================================
+template <class T>
+__global__ void __launch_bounds__(256)
+    cgs_up_kernel(int64_t n, const T* r, T* u, T* p, const T* q, const TqState* st) {
+  if (*(volatile const int*)&st->done != kRunning) return;
+  const cx<T> be = to_t<T>(st->beta);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> qv = ldc(q, e);
+    const cx<T> uv = ldc(r, e) + be * qv;
+    stc(u, e, uv);
+    stc(p, e, uv + be * (qv + be * ldc(p, e)));
+  }
+}
+
+// q = u - alpha v, w = u + q (w overwrites u).
+template <class T>
+__global__ void __launch_bounds__(256)
+    cgs_qw_kernel(int64_t n, T* u, T* q, const T* v, const TqState* st) {
+  if (*(volatile const int*)&st->done != kRunning) return;
+  const cx<T> al = to_t<T>(st->alpha);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> uv = ldc(u, e);
+    const cx<T> qv = uv - al * ldc(v, e);
+    stc(q, e, qv);
+    stc(u, e, uv + qv);
+  }
+}
+
+// x += alpha w, r -= alpha A w; ||r||^2 and <rh, r>.
+template <class T>
+__global__ void __launch_bounds__(256)
+    cgs_xr_kernel(int64_t n, T* x, T* r, const T* w, const T* aw, const T* rh, TqState* st,
+                  double* part) {
+  __shared__ double lds[3 * 4];
+  if (*(volatile int*)&st->done != kRunning) return;
+  const cx<T> al = to_t<T>(st->alpha);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    stc(x, e, ldc(x, e) + al * ldc(w, e));
+    const cx<T> rv = ldc(r, e) - al * ldc(aw, e);
+    stc(r, e, rv);
+    acc[0] += cabs2_d(rv);
+    const cx<double> d = cdotc_d(ldc(rh, e), rv);
+    acc[1] += d.re;
+    acc[2] += d.im;
+  }
+  block_partial<3>(acc, part, lds);
+}
+
+// End of a CGS iteration: the stopping tests on the recursive residual, then
+// beta = rho' / rho for the next one.
+struct CgsFinish {
+  TqState* st;
+  __device__ bool skip() const { return *(volatile int*)&st->done != kRunning; }
+  __device__ void operator()(const double* s) const {
+    const double rr = s[0];
+    const cx<double> rho_new{s[1], s[2]};
+    st->iter += 1;
+    if (st->hist && st->iter <= st->hist_len) st->hist[st->iter - 1] = sqrt(rr) * st->hscale;
+    if (!isfinite(rr) || !isfinite(s[1]) || !isfinite(s[2])) {
+      st->done = kNan;
+      return;
+    }
+    st->rr = rr;
+    if (rr <= st->tol2) {
+      st->done = kConverged;
+      return;
+    }
+    if (cabs2(st->rho) == 0.0 || cabs2(rho_new) == 0.0) {
+      st->reason = 3;
+      st->done = kBreakdown;
+      return;
+    }
+    st->beta = cdiv_d(rho_new, st->rho);
+    st->rho = rho_new;
+    if (st->iter >= st->max_iter) st->done = kMaxIter;
+  }
+};
 
 // OpMatvec with the solver's stop flag: no work once the iteration ended.
 template <class T>

@@ -361,6 +361,11 @@ template <class T>
 struct TqVecs {
   T *x, *w, *u0, *u1, *au0, *au1, *v, *d, *rh;
 };
+// CGS vectors: x, r, the shadow, u (then w = u + q), p, q, v (A p, then A w).
+template <class T>
+struct CgsVecs {
+  T *x, *r, *rh, *u, *p, *q, *v;
+};
 
 template <class T>
 struct Inner {
@@ -369,6 +374,7 @@ struct Inner {
   GmVecs<T> gv;
   CrVecs<T> cr;
   TqVecs<T> tq;
+  CgsVecs<T> cg;
   T* rin;
   T* d;
   // true: the inner method applies the symmetric scaling itself (as a
@@ -799,6 +805,82 @@ static fit_status tfqmr(Ctx& c, TqVecs<T>& V, const T* r0v, double tol_rel, int 
   return FIT_OK;
 }
 
+// CGS on A_int x = r0v from x = 0.
+template <class T>
+static fit_status cgs(Ctx& c, CgsVecs<T>& V, const T* r0v, double tol_rel, int max_iter,
+                      int check_every, double hscale, double* hist_dev, int hist_len,
+                      int use_graph, uint64_t shadow_seed, int* done, int* iters) {
+  const int64_t ne = c.g->ne;
+  const int64_t nb = pw_blocks(ne);
+  fit_status st;
+  if ((st = vzero(c, V.x, ne)) != FIT_OK) return st;
+  if ((st = vzero(c, V.p, ne)) != FIT_OK) return st;
+  if ((st = vzero(c, V.q, ne)) != FIT_OK) return st;
+  if ((st = vcopy(c, r0v, V.r, ne)) != FIT_OK) return st;
+  if ((st = xform<T, T, XF_SHADOW>(c, false, false, V.r, V.rh, 1.0, false, shadow_seed)) != FIT_OK)
+    return st;
+  hipLaunchKernelGGL(dot_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, V.rh, V.r, ne, c.red,
+                     c.part, c.cnt);
+  FIT_HIP(hipGetLastError());
+  FIT_HIP(launch_finish<4>(c.part, (int)nb, StoreSums<4>{c.red}, c.s));
+  if ((st = sync_copy(c, c.h_red, c.red, sizeof(RedOut))) != FIT_OK) return st;
+  const double r0 = c.h_red->v[3];
+  *iters = 0;
+  if (!(r0 > 0.0) || !std::isfinite(r0)) {
+    *done = r0 == 0.0 ? kConverged : kNan;
+    return FIT_OK;
+  }
+  TqState h{};
+  h.rho = cx<double>{c.h_red->v[0], c.h_red->v[1]};
+  h.beta = cx<double>{0.0, 0.0};
+  h.rr = r0;
+  h.tol2 = tol_rel * tol_rel * r0;
+  h.hscale = hscale / std::sqrt(r0);
+  h.max_iter = max_iter;
+  h.done = kRunning;
+  h.hist = hist_dev;
+  h.hist_len = hist_len;
+  FIT_HIP(hipMemcpyAsync(c.tst, &h, sizeof(TqState), hipMemcpyHostToDevice, c.s));
+  const int* dflag = &c.tst->done;
+  auto one_iter = [&]() -> fit_status {
+    fit_status e;
+    const int tok = prof_begin(c.s);
+    hipLaunchKernelGGL(cgs_up_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.r, V.u, V.p,
+                       V.q, c.tst);
+    FIT_HIP(hipGetLastError());
+    prof_end(tok, c.s, sizeof(T) == 8 ? "cgs_update_c128" : "cgs_update_c64");
+    OpMatvecIf<T> m1{V.p, V.v, dflag};
+    if ((e = launch_op_stencil_mode<T>(c, c.sym, m1)) != FIT_OK) return e;
+    hipLaunchKernelGGL(tq_dot_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.rh, V.v,
+                       c.tst, c.part);
+    FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<2>(c.part, (int)nb, TqAlphaFinish{c.tst}, c.s));
+    hipLaunchKernelGGL(cgs_qw_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.u, V.q, V.v,
+                       c.tst);
+    FIT_HIP(hipGetLastError());
+    OpMatvecIf<T> m2{V.u, V.v, dflag};  // A w into v (v is free again)
+    if ((e = launch_op_stencil_mode<T>(c, c.sym, m2)) != FIT_OK) return e;
+    hipLaunchKernelGGL(cgs_xr_kernel<T>, dim3((unsigned)nb), dim3(256), 0, c.s, ne, V.x, V.r, V.u,
+                       V.v, V.rh, c.tst, c.part);
+    FIT_HIP(hipGetLastError());
+    FIT_HIP(launch_finish<3>(c.part, (int)nb, CgsFinish{c.tst}, c.s));
+    return FIT_OK;
+  };
+  // two operator applications (4 passes) and about 18 vector passes
+  const double per_iter_bytes = node_bytes(c.g, 22, sizeof(T));
+  if (check_every <= 0) check_every = 2 * std::max(1, std::min(50, (int)(2e8 / (double)ne)));
+  bool stalled = false;
+  const int stall_window = sizeof(T) == 4 ? 1500 : 6000;
+  if ((st = poll_iterations(c, one_iter, check_every, use_graph, c.tst, c.h_tst, per_iter_bytes, 2,
+                            stall_window, &stalled)) != FIT_OK)
+    return st;
+  *done = stalled ? kBreakdown : c.h_tst->done;
+  *iters = c.h_tst->iter;
+  c.last_reason = stalled ? 9 : c.h_tst->reason;
+  c.last_rr = c.h_tst->rr / r0;
+  return FIT_OK;
+}
+
 template <class T>
 static size_t inner_bytes(int64_t ne, int solver, int m) {
   const size_t v = align_up((size_t)ne * 2 * sizeof(T), 256);
@@ -806,6 +888,7 @@ static size_t inner_bytes(int64_t ne, int solver, int m) {
   if (solver == FIT_COCG) return 8 * v;
   if (solver == FIT_COCR) return 6 * v;
   if (solver == FIT_TFQMR) return 10 * v;
+  if (solver == FIT_CGS) return 8 * v;
   const int nblk = (int)((ne + 256 * kMdPer - 1) / (256 * kMdPer));
   return (size_t)(2 * m + 5) * v + align_up(sizeof(double) * 2 * (size_t)(m + 1) * nblk, 256);
 }
@@ -857,6 +940,15 @@ static void inner_carve(Arena& a, Inner<T>& in, int64_t ne, int solver, int m) {
     in.tq.d = a.take<T>(v);
     in.tq.rh = a.take<T>(v);
     in.d = in.tq.x;
+  } else if (solver == FIT_CGS) {
+    in.cg.x = a.take<T>(v);
+    in.cg.r = a.take<T>(v);
+    in.cg.rh = a.take<T>(v);
+    in.cg.u = a.take<T>(v);
+    in.cg.p = a.take<T>(v);
+    in.cg.q = a.take<T>(v);
+    in.cg.v = a.take<T>(v);
+    in.d = in.cg.x;
   } else {
     const size_t vv = align_up(v, 256);
     in.gv.ldv = (int64_t)(vv / (2 * sizeof(T)));
@@ -900,6 +992,11 @@ static fit_status run_inner(Ctx& c, Inner<T>& in, double q, int max_iter, int ch
     return tfqmr<T>(c, in.tq, in.rin, q, max_iter, check_every, hscale, hist, hist_len, use_graph,
                     seed, done, iters);
   }
+  if (in.solver == FIT_CGS) {
+    const uint64_t seed = kShadowSeed + (uint64_t)in.restarts++;
+    return cgs<T>(c, in.cg, in.rin, q, max_iter, check_every, hscale, hist, hist_len, use_graph,
+                  seed, done, iters);
+  }
   return gmres<T>(c, in.gv, in.m, q, max_iter, hscale, hist, hist_len, pre, in.rin, nullptr,
                   done, iters, &tmp, 0.0);
 }
@@ -937,7 +1034,7 @@ fit_status refine(Ctx& c, Inner<T>& in, const double* b, double bnorm, double* x
   // is spent: a correction that does not lower the true residual is undone
   // and the next inner solve starts again from the best iterate.  Only a
   // long run of inner solves without halving the residual ends it early.
-  const bool retry = in.solver == FIT_BICGSTAB || in.solver == FIT_TFQMR;
+  const bool retry = in.solver == FIT_BICGSTAB || in.solver == FIT_TFQMR || in.solver == FIT_CGS;
   const int max_no_progress = retry ? (sizeof(T) == 4 ? 6 : 64) : 4;
   for (;;) {
     // inner rhs: S r scaled to unit norm, in precision T (S r = eta * rin)
@@ -1091,7 +1188,7 @@ fit_status solve_impl(fit_grid* g, double omega, const void* source_dev, double 
   if (opts) o = *opts;
   if (o.restart == 0) o.restart = 30;
   if (o.max_iters <= 0) o.max_iters = 100000;
-  if (o.solver < FIT_BICGSTAB || o.solver > FIT_TFQMR || o.restart < 1 ||
+  if (o.solver < FIT_BICGSTAB || o.solver > FIT_CGS || o.restart < 1 ||
       o.restart > kMaxRestart || (o.precision != FIT_PREC_FP64 && o.precision != FIT_PREC_MIXED) ||
       (o.scaling != FIT_SCALE_NONE && o.scaling != FIT_SCALE_SYM) || o.resid_history_len < 0 ||
       (o.resid_history_len > 0 && !o.resid_history) || o.diag < FIT_DIAG_AUTO ||

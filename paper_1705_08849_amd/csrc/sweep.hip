@@ -761,9 +761,11 @@ extern "C" fit_status fit_autotune_sweep(fit_grid* g, const double* omegas, int 
     g_sweep_batch.store(4);
     st = run(std::min(nomega, 4), iters, &w, &wi);
   }
-  for (int b : {4, 8, 16, 32, 64}) {
+  // largest batch first: a smaller batch must be more than 2 % faster to
+  // replace it (fewer batches mean fewer serial tails of slow systems)
+  for (int b : {64, 32, 16, 8, 4}) {
     if (st != FIT_OK) break;
-    if (b > nomega && b != 4) break;
+    if (b > nomega && b != 4 && b / 2 >= nomega) continue;
     g_sweep_batch.store(b);
     const int nf = std::min(nomega, b);
     double secs[2] = {0.0, 0.0};
@@ -775,7 +777,7 @@ extern "C" fit_status fit_autotune_sweep(fit_grid* g, const double* omegas, int 
     // system-iterations per second of the iteration itself (the difference
     // of the two runs removes set-up and graph capture)
     const double rate = (double)(its[1] - its[0]) / std::max(secs[1] - secs[0], 1e-9);
-    if (rate > 1.02 * best) {
+    if (best < 0.0 || rate > 1.02 * best) {
       best = rate;
       best_b = b;
     }

@@ -23,12 +23,12 @@ STATUS_NAMES = ["FIT_OK", "FIT_E_INVALID", "FIT_E_NOMEM", "FIT_E_DEVICE", "FIT_E
                 "FIT_E_BREAKDOWN", "FIT_E_NAN", "FIT_E_UNSUPPORTED"]
 C128, C64 = 0, 1
 SCALE_NONE, SCALE_SYM, SCALE_FACT = 0, 1, 2
-BICGSTAB, GMRES, FGMRES, COCG, COCR, TFQMR = 0, 1, 2, 3, 4, 5
+BICGSTAB, GMRES, FGMRES, COCG, COCR, TFQMR, CGS = 0, 1, 2, 3, 4, 5, 6
 PREC_FP64, PREC_MIXED = 0, 1
 DIAG_AUTO, DIAG_MASS, DIAG_PAPER, DIAG_JACOBI = 0, 1, 2, 3
 
 SOLVERS = {"bicgstab": BICGSTAB, "gmres": GMRES, "fgmres": FGMRES, "cocg": COCG, "cocr": COCR,
-           "tfqmr": TFQMR}
+           "tfqmr": TFQMR, "cgs": CGS}
 SCALINGS = {"none": SCALE_NONE, "sym": SCALE_SYM, "fact": SCALE_FACT}
 PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
 DIAGS = {"auto": DIAG_AUTO, "mass": DIAG_MASS, "paper": DIAG_PAPER, "jacobi": DIAG_JACOBI}

@@ -125,11 +125,12 @@ def test_stored_diagonal_needs_cocg():
     assert e.value.status == fit.E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("method", ["cocr", "tfqmr"])
+@pytest.mark.parametrize("method", ["cocr", "tfqmr", "cgs"])
 def test_cocr_and_tfqmr_recurrences_track_the_oracle(method):
-    """The two further methods of the paper's comparison (Sec. IV) follow
-    the oracle's textbook recurrences step by step on the scaled system:
-    COCR's recursive residual, TFQMR's QMR bound tau sqrt(m + 1)."""
+    """The further methods of the paper's comparison (Sec. IV) follow the
+    oracle's textbook recurrences step by step on the scaled system:
+    COCR's and CGS's recursive residuals, TFQMR's QMR bound tau
+    sqrt(m + 1)."""
     dev = D.layered_device(40, 36, 30, n_layers=4, n_strips=3, n_ports=1, seed=12)
     g = fit.Grid(dev)
     om = 2 * np.pi * 10e9
@@ -144,16 +145,19 @@ def test_cocr_and_tfqmr_recurrences_track_the_oracle(method):
     b = s * O.rhs(dev, om, src)
     if method == "cocr":
         xs, _, _, hc = O.cocr(a, b, tol=1e-14, maxiter=nit, history=True)
-    else:
+    elif method == "tfqmr":
         rhat = O.shadow_vector(dev.n_edges)[O.free_edges(dev)]
         xs, _, _, hc = O.tfqmr(a, b, rhat, tol=1e-14, maxiter=nit, history=True)
+    else:
+        rhat = O.shadow_vector(dev.n_edges)[O.free_edges(dev)]
+        xs, _, _, hc = O.cgs(a, b, rhat, tol=1e-14, maxiter=nit, history=True)
     n = min(len(hg), len(hc))
     rel = np.abs(hg[:n] - hc[:n]) / hc[:n]
     print(f"{method}: gpu {hg[:4]} cpu {hc[:4]} max rel diff {rel.max():.2e}")
     assert n == nit and rel[:20].max() < 1e-8 and rel.max() < 1e-4
 
 
-@pytest.mark.parametrize("method", ["cocr", "tfqmr"])
+@pytest.mark.parametrize("method", ["cocr", "tfqmr", "cgs"])
 def test_cocr_and_tfqmr_solve(method):
     dev = D.layered_device(24, 20, 12, n_layers=3, n_strips=2, n_ports=2, seed=21)
     g = fit.Grid(dev)

@@ -707,10 +707,10 @@ def test_mutation_scaled_curl_without_square_root_is_caught(monkeypatch):
         test_paper_diagonal_preconditioner_closed_form(0x3F)
 
 
-@pytest.mark.parametrize("method", ["cocr", "tfqmr"])
+@pytest.mark.parametrize("method", ["cocr", "tfqmr", "cgs"])
 def test_cocr_and_tfqmr_reach_the_direct_solution(method):
-    """The two further methods of the paper's solver comparison (Sec. IV:
-    CR in complex symmetric form, and TFQMR) on a small lossy graded device,
+    """The further methods of the paper's solver comparison (Sec. IV: CR in
+    complex symmetric form, TFQMR and CGS) on a small lossy graded device,
     scaled as in eq. (e2t): the iterate reaches the sparse direct solution."""
     dev = D.layered_device(9, 8, 7, n_layers=3, n_strips=1, n_ports=1, seed=13)
     om = 2 * np.pi * 9e9
@@ -718,10 +718,13 @@ def test_cocr_and_tfqmr_reach_the_direct_solution(method):
     a = (sp.diags(s) @ O.system_matrix(dev, om) @ sp.diags(s)).tocsr()
     src = D.port_source(dev, 0)
     b = s * O.rhs(dev, om, src)
+    rhat = O.shadow_vector(dev.n_edges)[O.free_edges(dev)]
     if method == "cocr":
         x, it, rr = O.cocr(a, b, tol=1e-11)
+    elif method == "tfqmr":
+        x, it, rr = O.tfqmr(a, b, rhat, tol=1e-11)
     else:
-        x, it, rr = O.tfqmr(a, b, O.shadow_vector(dev.n_edges)[O.free_edges(dev)], tol=1e-11)
+        x, it, rr = O.cgs(a, b, rhat, tol=1e-11)
     ref = O.solve_direct(dev, om, src)[O.free_edges(dev)]
     assert rr <= 1e-9
     assert np.linalg.norm(s * x - ref) <= 1e-6 * np.linalg.norm(ref)
@@ -742,3 +745,32 @@ def test_cocr_minimises_the_residual_on_a_hermitian_positive_system():
     for k in (5, 10, 20):
         _, _, rg = O.gmres(sp.csr_matrix(a.astype(np.complex128)), b, restart=k, tol=1e-16, maxiter=k)
         assert h[k - 1] <= rg * (1 + 1e-8)
+
+
+def test_cgs_residual_is_the_squared_bicg_polynomial():
+    """CGS applies the BiCG residual polynomial twice: on a real symmetric
+    positive definite matrix with the shadow vector r0 (where BiCG is CG),
+    ||r_k^CGS|| = ||phi_k(A)^2 r0|| with phi_k from CG's own recurrence."""
+    rng = np.random.default_rng(5)
+    q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    lam = np.linspace(1, 9, 40)
+    a = (q * lam) @ q.T
+    b = rng.standard_normal(40).astype(np.complex128)
+    am = sp.csr_matrix(a.astype(np.complex128))
+    _, _, _, h = O.cgs(am, b, b.copy(), tol=1e-30, maxiter=6, history=True)
+    # CG's residual polynomial through the Lanczos recurrence, as a matrix
+    r = b.copy(); p = r.copy(); rr = np.vdot(r, r)
+    phis = []
+    poly_r = np.eye(40); poly_p = np.eye(40)
+    for k in range(6):
+        ap = a @ p
+        alpha = rr / np.vdot(p, ap)
+        poly_r_new = poly_r - alpha * (a @ poly_p)
+        r = r - alpha * ap
+        rr_new = np.vdot(r, r)
+        beta = rr_new / rr
+        poly_p = poly_r_new + beta * poly_p
+        p = r + beta * p
+        poly_r, rr = poly_r_new, rr_new
+        phis.append(np.linalg.norm(poly_r @ poly_r @ b) / np.linalg.norm(b))
+    np.testing.assert_allclose(h, phis, rtol=1e-8)
