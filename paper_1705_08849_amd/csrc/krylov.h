@@ -62,6 +62,7 @@ struct OpCocgPX {
   };
   static constexpr int NRED = 2;
   static constexpr bool kFused = true;
+  static constexpr bool kDeepPrefetch = true;
   __device__ bool skip() const { return *(volatile int*)&st->done != kRunning; }
   __device__ void begin() {
     beta = cx<T>{(T)st->beta.re, (T)st->beta.im};
@@ -379,6 +380,7 @@ struct OpResidual {
     cx<T> v[3];
   };
   static constexpr int NRED = 1;
+  static constexpr bool kDeepPrefetch = true;
   __device__ bool skip() const { return false; }
   __device__ void begin() {}
   __device__ void load(int64_t n, Raw& a) const {

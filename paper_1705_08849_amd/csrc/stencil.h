@@ -190,6 +190,18 @@ template <class Op>
 struct OpFused<Op, std::void_t<decltype(Op::kFused)>> {
   static constexpr bool value = Op::kFused;
 };
+// Ops that set kDeepPrefetch = true have each plane's loads issued two plane
+// steps before the step that consumes them instead of one: both prefetch
+// buffers stay live, which costs about 30 VGPRs (still two waves per SIMD in
+// complex128) and keeps two planes of loads in flight per wave.
+template <class Op, class = void>
+struct OpDeep {
+  static constexpr bool value = false;
+};
+template <class Op>
+struct OpDeep<Op, std::void_t<decltype(Op::kDeepPrefetch)>> {
+  static constexpr bool value = Op::kDeepPrefetch;
+};
 
 // Body of one workgroup: logical tile lb of the launch L on grid g.  Its
 // reduction partials go to op.partials() at index lb.
@@ -202,6 +214,11 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
   constexpr bool SYM = (MODE == MODE_MEC || MODE == MODE_FACT);
   constexpr bool FACT = (MODE == MODE_FACT);
   constexpr int NR = Op::NRED > 0 ? Op::NRED : 1;
+  // Complex128 only (in complex64 the extra registers cost a wave per SIMD,
+  // which measured slower), and the fused ops keep the shallow pipeline in
+  // the scaled modes, where the deep one would spill.
+  constexpr bool DEEP =
+      OpDeep<Op>::value && sizeof(T) == 8 && !(SYM && OpFused<Op>::value);
 
   op.begin();
 
@@ -252,12 +269,13 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
 
   PlaneRec<T> lo = plane_rec(mat, cg, inb ? load_cell_ids(g, i, j, ks - 1) : 0xFFFFFFFFu);
 
-  // Prefetch pipeline.  fetch(q) loads plane q's vector data, cell ids and
-  // z-geometry into one of two buffers; process(q) consumes that buffer one
-  // step later.  The buffers alternate (the loop below is unrolled by two),
-  // so every load lands in registers that stay put until it is consumed: no
-  // register copy -- and hence no wait on the vector memory counter, which
-  // would also drain the prefetch behind it -- happens in between.
+  // Prefetch pipeline.  fetch(q) loads plane q's vector data and cell ids
+  // into one of two buffers; process(q) consumes that buffer one step later
+  // (two steps with DEEP).  The buffers alternate (the loop below is unrolled
+  // by two), so every load lands in registers that stay put until it is
+  // consumed: no register copy -- and hence no wait on the vector memory
+  // counter, which would also drain the prefetch behind it -- happens in
+  // between.
   struct Pending {
     typename Op::Raw raw;
     CellIdsRaw ids;
@@ -319,7 +337,7 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
     cur_mask = sn.mask;
   };
 
-  // ---- prologue: stage planes ks and ks+1, prefetch ks+2 -----------------
+  // ---- prologue: stage planes ks and ks+1, prefetch ks+2 (and ks+3) -------
   fetch(ks, pa);
   process(ks, pa);
   stage_lds(0);
@@ -327,6 +345,7 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
   fetch(ks + 1, pb);
   process(ks + 1, pb);
   fetch(ks + 2, pa);
+  if constexpr (DEEP) fetch(ks + 3, pb);
   __syncthreads();
 
   double acc[NR];
@@ -336,7 +355,8 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
 
   // One plane step (plane k in LDS buffer b): facets of plane k, plane k+1
   // into buffer b^1, one barrier, gather onto plane k's edges, then stage
-  // plane k+2 from `use` and prefetch plane k+3 into `next`.  Buffer b's
+  // plane k+2 from `use` and prefetch plane k+3 into `next` (DEEP: plane k+4
+  // into `use`, while `next` still holds plane k+3 in flight).  Buffer b's
   // facets are rewritten two steps later, after the next barrier, which
   // every reader of them has passed; buffer b^1's values were last read
   // before the previous barrier.
@@ -391,7 +411,11 @@ __device__ __forceinline__ void stencil_body(const GridView& g, const StencilLau
     // ---- advance: plane k+1 becomes current, stage k+2, prefetch k+3 ------
     advance_regs();
     process(k + 2, use);
-    fetch(k + 3, next);
+    if constexpr (DEEP) {
+      fetch(k + 4, use);
+    } else {
+      fetch(k + 3, next);
+    }
   };
 
   int k = ks;
@@ -540,6 +564,7 @@ struct OpMatvec {
     cx<T> v[3];
   };
   static constexpr int NRED = 0;
+  static constexpr bool kDeepPrefetch = true;
   __device__ bool skip() const { return false; }
   __device__ void begin() {}
   __device__ void load(int64_t n, Raw& r) const {
