@@ -215,6 +215,65 @@ def sweep_row(fit, D, np, torch, with_cpu):
     return row
 
 
+def baseline_row(fit, D, np, torch):
+    """The batched sweep against the plain method of the comparison: every
+    one of 64 log-spaced frequencies (1-40 GHz) on the smallest sweep-family
+    grid, port 1 excitation, to a true relative residual of 1e-8, solved by
+    complex128 BiCGStab one fit_solve at a time (capped at 60k iterations)
+    and by fit_sweep (COCG, complex128 and the mixed form).  The speedup is
+    quoted on the frequencies the plain BiCGStab reaches 1e-8 at, re-solved
+    there by the sweep, so both sides are timed at the same accuracy on the
+    same systems.  Not part of the default run (about four minutes)."""
+    dev = D.sweep_devices()[0]
+    g = fit.Grid(dev)
+    oms = D.log_spaced_omegas(64)
+    src = torch.from_numpy(D.port_source(dev, 0)).to("cuda:0")
+    g.autotune_solver(float(oms[32]), iters=40)
+    batch, _ = g.autotune_sweep(oms[:16], iters=40)
+    fit.sweep([g], oms[:2], [src[None, :]], tol=1e-8)  # warm-up
+    torch.cuda.synchronize()
+
+    def run_sweep(om_list, prec):
+        t0 = time.perf_counter()
+        _, _, infos = fit.sweep([g], om_list, [src[None, :]], tol=1e-8, max_iters=60000, precision=prec)
+        torch.cuda.synchronize()
+        ok = sum(1 for i in infos if i["status"] == 0 and i["true_relres"] <= 1e-8)
+        return time.perf_counter() - t0, ok
+
+    full = {p: run_sweep(oms, p) for p in ("fp64", "mixed")}
+    conv, t_conv, t_all = [], 0.0, 0.0
+    for k, om in enumerate(oms):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = g.solve(float(om), src, tol=1e-8, solver="bicgstab", max_iters=60000,
+                          raise_on_error=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_all += dt
+        if info["status_name"] == "FIT_OK" and info["true_relres"] <= 1e-8:
+            conv.append(k)
+            t_conv += dt
+        if k % 16 == 15:
+            print(f"bench.py: plain BiCGStab {k + 1}/64 frequencies, {len(conv)} at 1e-8",
+                  file=sys.stderr, flush=True)
+    row = {"workload": "64x64x32-cell sweep-family device (seed 40), 64 log-spaced frequencies "
+                       "1-40 GHz, port 1, true relative residual 1e-8",
+           "systems_per_batch": batch,
+           "plain_bicgstab_c128": {"wall_s": round(t_all, 2), "converged": len(conv), "of": 64},
+           "sweep_cocg_c128": {"wall_s": round(full["fp64"][0], 2), "converged": full["fp64"][1], "of": 64},
+           "sweep_cocg_mixed": {"wall_s": round(full["mixed"][0], 2), "converged": full["mixed"][1], "of": 64}}
+    if conv:
+        sub = oms[conv]
+        s64, ok64 = run_sweep(sub, "fp64")
+        smx, okmx = run_sweep(sub, "mixed")
+        row["matched"] = {"frequencies_GHz": [round(o / 2 / np.pi / 1e9, 2) for o in sub],
+                          "plain_bicgstab_s": round(t_conv, 2),
+                          "sweep_cocg_c128_s": round(s64, 2), "sweep_cocg_c128_converged": ok64,
+                          "sweep_cocg_mixed_s": round(smx, 2), "sweep_cocg_mixed_converged": okmx,
+                          "speedup_c128": round(t_conv / s64, 2), "speedup_mixed": round(t_conv / smx, 2)}
+    return row
+
+
 def _sweep_cpu_point(arg):
     """One sweep point of the oracle in a pool worker (one thread):
     assembly and scaling, 20 COCG iterations, extrapolated to `iters`."""
@@ -427,7 +486,7 @@ def main():
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the secondary rows (256x256x128 interconnect, batched sweep, learned "
                          "preconditioner): only the bench grid runs")
-    ap.add_argument("--row", choices=["sweep", "precond", "interconnect"],
+    ap.add_argument("--row", choices=["sweep", "precond", "interconnect", "baseline"],
                     help="run only this secondary row and print it as one JSON line")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short sample profiled by the HBM-counter passes")
@@ -473,6 +532,8 @@ def main():
         torch.cuda.init()
         if args.row == "interconnect":
             row = interconnect_row(fit, D, np, torch, mean_us)
+        elif args.row == "baseline":
+            row = baseline_row(fit, D, np, torch)
         else:
             fn = {"sweep": sweep_row, "precond": precond_row}[args.row]
             row = fn(fit, D, np, torch, not args.no_cpu_baseline)
