@@ -14,6 +14,12 @@
 
 namespace fit {
 
+// Block partial sums per block that the context's partials buffer holds
+// (every reduction launched through it writes at most this many per block:
+// the launches of the solvers' kernels and the operator launches, whose
+// width launch_op_stencil_mode checks at compile time).
+constexpr int kPartWidth = 4;
+
 // ---------------------------------------------------------------------------
 // Host-side solver context.
 // ---------------------------------------------------------------------------
@@ -59,6 +65,7 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 template <class T, class Op>
 static fit_status launch_op_stencil_mode(Ctx& c, bool sym, const Op& op) {
+  static_assert(Op::NRED <= kPartWidth, "the partials buffer holds kPartWidth sums per block");
   const TileShape t = sizeof(T) == 8 ? c.tile128 : c.tile64;
   if (sym) return launch_stencil<T, MODE_MEC>(c.g->view, t, c.omega, op, c.s);
   return launch_stencil<T, MODE_D>(c.g->view, t, c.omega, op, c.s);
@@ -132,7 +139,7 @@ inline fit_status setup_ctx(Ctx& c, fit_grid* g, double omega, int sym, hipStrea
   const int b128 = launch_blocks(make_launch(g->view, c.tile128, omega));
   const int b64 = launch_blocks(make_launch(g->view, c.tile64, omega));
   c.max_blocks = std::max(std::max(b128, b64), 4096);
-  const size_t need = align_up(sizeof(double) * 4 * (size_t)c.max_blocks, 256) + 256 +
+  const size_t need = align_up(sizeof(double) * kPartWidth * (size_t)c.max_blocks, 256) + 256 +
                       align_up(sizeof(RedOut), 256) + align_up(sizeof(BiState), 256) +
                       align_up(sizeof(GmState), 256) + align_up(sizeof(CgState), 256) +
                       align_up(sizeof(TqState), 256);
@@ -140,7 +147,7 @@ inline fit_status setup_ctx(Ctx& c, fit_grid* g, double omega, int sym, hipStrea
   if (st != FIT_OK) return st;
   char* p = (char*)g->red.ptr;
   c.part = (double*)p;
-  p += align_up(sizeof(double) * 4 * (size_t)c.max_blocks, 256);
+  p += align_up(sizeof(double) * kPartWidth * (size_t)c.max_blocks, 256);
   c.cnt = (unsigned*)p;
   p += 256;
   c.red = (RedOut*)p;
