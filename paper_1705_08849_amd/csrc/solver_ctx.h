@@ -138,7 +138,10 @@ inline fit_status setup_ctx(Ctx& c, fit_grid* g, double omega, int sym, hipStrea
   c.tile64 = tile_for(g, FIT_C64);
   const int b128 = launch_blocks(make_launch(g->view, c.tile128, omega));
   const int b64 = launch_blocks(make_launch(g->view, c.tile64, omega));
-  c.max_blocks = std::max(std::max(b128, b64), 4096);
+  // room for one update-kernel block per item (a grid-stride loop over
+  // several items per block was 8 % slower on the 256x256x128 grid)
+  const int b_upd = otf_shape(g->view, 1 << 30).blocks;
+  c.max_blocks = std::max(std::max(std::max(b128, b64), b_upd), 4096);
   const size_t need = align_up(sizeof(double) * kPartWidth * (size_t)c.max_blocks, 256) + 256 +
                       align_up(sizeof(RedOut), 256) + align_up(sizeof(BiState), 256) +
                       align_up(sizeof(GmState), 256) + align_up(sizeof(CgState), 256) +
