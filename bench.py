@@ -174,8 +174,13 @@ def sweep_row(fit, D, np, torch, with_cpu):
     sd = D.sweep_devices(seeds=[40], shapes=[(64, 64, 32)])[0]
     g = fit.Grid(sd)
     oms = D.log_spaced_omegas(16, 5e9, 40e9)
-    g.autotune_solver(float(oms[8]), iters=40)
-    batch, _ = g.autotune_sweep(oms, iters=40)
+    # an iteration on this grid takes ~20 us: 400-iteration timings keep the
+    # tile and batch choices from changing run to run.  Each side runs with
+    # its own tuned block shape: the solver tuner's for one system at a time,
+    # the sweep tuner's (chosen on batched launches) for the sweep.
+    tile, _ = g.autotune_solver(float(oms[8]), iters=400)
+    batch, _ = g.autotune_sweep(oms, iters=200)
+    sweep_tile = g.tile("c128")
     src = torch.from_numpy(D.port_source(sd, 0)).to("cuda:0")
     fit.sweep([g], oms[:2], [src[None, :]], tol=1e-8)  # warm-up
     torch.cuda.synchronize()
@@ -183,6 +188,9 @@ def sweep_row(fit, D, np, torch, with_cpu):
     st, _, infos = fit.sweep([g], oms, [src[None, :]], tol=1e-8, precision="fp64")
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    g.set_tile("c128", *tile)
+    g.solve(float(oms[0]), src, tol=1e-8, solver="cocg", max_iters=40, raise_on_error=False)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for om in oms:
         g.solve(float(om), src, tol=1e-8, solver="cocg", raise_on_error=False)
@@ -191,7 +199,8 @@ def sweep_row(fit, D, np, torch, with_cpu):
     iters = [i["iterations"] for i in infos]
     row = {"workload": "64x64x32-cell sweep-family device (seed 40), 16 log-spaced frequencies "
                        "5-40 GHz, one port excitation, COCG fp64 to 1e-8",
-           "status": fit.STATUS_NAMES[st], "points": 16, "systems_per_batch": batch,
+           "status": fit.STATUS_NAMES[st], "points": 16, "tile_sequential": list(tile),
+           "tile_batched": list(sweep_tile), "systems_per_batch": batch,
            "batched_points_per_s": round(16 / tb, 3),
            "sequential_points_per_s": round(16 / ts, 3), "speedup": round(ts / tb, 3),
            "iterations": [min(iters), max(iters)]}

@@ -341,6 +341,11 @@ fit_status fit_port_network(int nports, double z0, const double *zl, double *z_o
  * FIT_E_INVALID for a shape that is not compiled or zc outside [1, 128]. */
 fit_status fit_tile_set(const struct fit_grid *g, int dtype, int tx, int ty, int zc);
 
+/* The tile shape that launches on g in `dtype` use now (the table's entry
+ * for its node dimensions, else the default shape).  FIT_E_INVALID for a
+ * NULL grid or output pointer, or a bad dtype. */
+fit_status fit_tile_get(const struct fit_grid *g, int dtype, int32_t *tx, int32_t *ty, int32_t *zc);
+
 /* Time every compiled (TX, TY) with a range of ZC on g (operator in `dtype`
  * and `scaling` at omega, `reps` timed launches each, HIP events on `stream`),
  * record the fastest in the table and report it.  Candidates are timed in a
@@ -367,13 +372,17 @@ fit_status fit_autotune_solver(struct fit_grid *g, double omega, int iters, void
  * per-system results do not depend on it. */
 fit_status fit_sweep_set_batch(int systems);
 
-/* Choose fit_sweep's systems per batch for grids like g: time `iters` COCG
- * iterations (difference of runs of iters and 2 iters) of batches of 4, 8,
- * 16, 32 and 64 systems (frequencies taken from omegas, at most nomega), one
- * source of 1 A on every free edge, and keep the batch size with the most
- * system-iterations per second, candidates from the largest down (a smaller
- * one must win by more than 2 %: fewer batches leave fewer serial tails).
- * Sets the process-wide batch size; reports it and its rate.  Synchronous. */
+/* Choose fit_sweep's launch shape for grids like g: time `iters` COCG
+ * iterations (difference of runs of iters and 2 iters) of batched sweeps
+ * (frequencies taken from omegas, at most nomega; one source of 1 A on every
+ * free edge).  First the complex128 block shape: every compiled shape with
+ * z-chunks of 4 and 8 planes on batches of up to 16 systems; the one with
+ * the most system-iterations per second (a later one must win by more than
+ * 2 %) is stored in the tile table for g's node dimensions, so later solves
+ * on such grids use it too.  Then the systems per batch: 64, 32, 16, 8 and 4,
+ * from the largest down (a smaller batch must win by more than 2 %: fewer
+ * batches leave fewer serial tails).  Sets the process-wide batch size;
+ * reports it and its rate.  Synchronous. */
 fit_status fit_autotune_sweep(struct fit_grid *g, const double *omegas, int nomega, int iters,
                               void *stream, int32_t *best_batch, double *best_rate);
 

@@ -761,22 +761,55 @@ extern "C" fit_status fit_autotune_sweep(fit_grid* g, const double* omegas, int 
     g_sweep_batch.store(4);
     st = run(std::min(nomega, 4), iters, &w, &wi);
   }
+  // system-iterations per second of the batched iteration itself for batches
+  // of b systems (the difference of two runs removes set-up and capture);
+  // negative if the runs stopped early
+  auto rate_of = [&](int b, double* rate) -> fit_status {
+    g_sweep_batch.store(b);
+    const int nf = std::min(nomega, b);
+    double secs[2] = {0.0, 0.0};
+    int64_t its[2] = {0, 0};
+    for (int rep = 0; rep < 2; ++rep) {
+      const fit_status e = run(nf, rep == 0 ? iters : 2 * iters, &secs[rep], &its[rep]);
+      if (e != FIT_OK) return e;
+    }
+    *rate = its[1] > its[0] ? (double)(its[1] - its[0]) / std::max(secs[1] - secs[0], 1e-9) : -1.0;
+    return FIT_OK;
+  };
+  // The complex128 block shape of the batched launches (every system of a
+  // launch uses the largest grid's shape): the compiled shapes with z-chunks
+  // of 4 and 8 planes, timed on batches of up to 16 systems; the best one is
+  // stored for the grid.  Shapes that suit one system at a time leave a
+  // batch of small grids too few workgroups per system.
+  const TileShape saved_tile = tile_for(g, FIT_C128);
+  TileShape best_t = saved_tile;
+  double best_tr = -1.0;
+  const TileShape cands[] = {{32, 16, 4}, {32, 16, 8}, {32, 8, 4}, {32, 8, 8},
+                             {48, 8, 4}, {48, 8, 8}, {64, 8, 4}, {64, 8, 8}};
+  for (const TileShape& t : cands) {
+    if (st != FIT_OK) break;
+    if (t.zc > g->view.nz) continue;
+    if ((st = fit_tile_set(g, FIT_C128, t.tx, t.ty, t.zc)) != FIT_OK) break;
+    double rate = -1.0;
+    if ((st = rate_of(16, &rate)) != FIT_OK) break;
+    if (rate > 0.0 && (best_tr < 0.0 || rate > 1.02 * best_tr)) {
+      best_tr = rate;
+      best_t = t;
+    }
+  }
+  {
+    const fit_status e = st == FIT_OK ? fit_tile_set(g, FIT_C128, best_t.tx, best_t.ty, best_t.zc)
+                                      : fit_tile_set(g, FIT_C128, saved_tile.tx, saved_tile.ty, saved_tile.zc);
+    if (st == FIT_OK) st = e;
+  }
   // largest batch first: a smaller batch must be more than 2 % faster to
   // replace it (fewer batches mean fewer serial tails of slow systems)
   for (int b : {64, 32, 16, 8, 4}) {
     if (st != FIT_OK) break;
     if (b > nomega && b != 4 && b / 2 >= nomega) continue;
-    g_sweep_batch.store(b);
-    const int nf = std::min(nomega, b);
-    double secs[2] = {0.0, 0.0};
-    int64_t its[2] = {0, 0};
-    for (int rep = 0; rep < 2 && st == FIT_OK; ++rep)
-      st = run(nf, rep == 0 ? iters : 2 * iters, &secs[rep], &its[rep]);
-    if (st != FIT_OK) break;
-    if (its[1] <= its[0]) continue;
-    // system-iterations per second of the iteration itself (the difference
-    // of the two runs removes set-up and graph capture)
-    const double rate = (double)(its[1] - its[0]) / std::max(secs[1] - secs[0], 1e-9);
+    double rate = -1.0;
+    if ((st = rate_of(b, &rate)) != FIT_OK) break;
+    if (rate < 0.0) continue;
     if (best < 0.0 || rate > 1.02 * best) {
       best = rate;
       best_b = b;

@@ -103,6 +103,18 @@ extern "C" fit_status fit_tile_set(const fit_grid* g, int dtype, int tx, int ty,
   return FIT_OK;
 }
 
+extern "C" fit_status fit_tile_get(const fit_grid* g, int dtype, int32_t* tx, int32_t* ty, int32_t* zc) {
+  if (!g || !tx || !ty || !zc || (dtype != FIT_C128 && dtype != FIT_C64)) {
+    set_error("fit_tile_get: NULL argument or bad dtype");
+    return FIT_E_INVALID;
+  }
+  const TileShape t = tile_for(g, dtype);
+  *tx = t.tx;
+  *ty = t.ty;
+  *zc = t.zc;
+  return FIT_OK;
+}
+
 extern "C" fit_status fit_autotune(const fit_grid* g, int dtype, int scaling, double omega,
                                    int reps, void* stream, int32_t* tx, int32_t* ty, int32_t* zc,
                                    double* best_us) {

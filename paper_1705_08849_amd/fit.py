@@ -145,6 +145,8 @@ _SIGS = [
                                       C.c_void_p, C.c_void_p, C.POINTER(C.c_int),
                                       C.POINTER(C.c_int)]),
     ("fit_tile_set", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]),
+    ("fit_tile_get", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                               C.POINTER(C.c_int32)]),
     ("fit_autotune_solver", C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_void_p,
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
@@ -260,6 +262,13 @@ class Grid:
     def set_tile(self, dtype: str, tx: int, ty: int, zc: int):
         check(lib().fit_tile_set(self.h, {"c128": C128, "c64": C64}[dtype], tx, ty, zc),
               "fit_tile_set")
+
+    def tile(self, dtype: str = "c128"):
+        """``fit_tile_get``: the (tx, ty, zc) that launches on this grid use now."""
+        tx, ty, zc = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().fit_tile_get(self.h, {"c128": C128, "c64": C64}[dtype], C.byref(tx), C.byref(ty),
+                                 C.byref(zc)), "fit_tile_get")
+        return tx.value, ty.value, zc.value
 
     def autotune(self, dtype: str = "c128", scaling: str = "none", omega: float = 2e10,
                  reps: int = 10, stream=None):
