@@ -389,10 +389,15 @@ def test_precision_form_complex64_does_the_work():
                           max_iters=40000)
         xh = x.cpu().numpy()
         rr = O.relative_residual(dev, om, src, xh)
-        ref = O.solve_direct(dev, om, src)
+        # forward error against an FP64 solve to 1e-12 (the residual bar
+        # above is the oracle's; a sparse direct solve of this size would
+        # spend minutes of host time on a number that is only reported)
+        x64, _ = g.solve(om, _cuda(src), tol=1e-12, solver="cocg", precision="fp64",
+                         max_iters=40000)
+        ref = x64.cpu().numpy()
         fe = np.linalg.norm(xh - ref) / np.linalg.norm(ref)
         print(f"{f / 1e9:.0f} GHz: iters {info['iterations']} refinements {info['refinements']} "
-              f"fell back {info['fell_back']} relres {rr:.2e} forward error vs fp64 direct {fe:.2e}")
+              f"fell back {info['fell_back']} relres {rr:.2e} forward error vs fp64 {fe:.2e}")
         assert info["fell_back"] == 0 and info["refinements"] >= 2
         assert rr <= 1e-8 and abs(rr - info["true_relres"]) <= 1e-9
 
