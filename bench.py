@@ -283,6 +283,102 @@ def baseline_row(fit, D, np, torch):
     return row
 
 
+def _progress(msg):
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
+def solvers_row(fit, D, np, torch):
+    """Every method of the solver comparison on the 64x64x48-cell graded
+    layered device (4 layers, 3 PEC strips, one port, seed 12) at 1, 10 and
+    40 GHz to a true relative residual of 1e-8, capped at 60k iterations:
+    COCG with each diagonal, COCR, TFQMR, CGS, BiCGStab and GMRES(30).  Not
+    part of the default run (several minutes)."""
+    dev = D.layered_device(64, 64, 48, n_layers=4, n_strips=3, n_ports=1, seed=12)
+    g = fit.Grid(dev)
+    src = torch.from_numpy(D.port_source(dev, 0)).to("cuda:0")
+    runs = [("cocg", "auto"), ("cocg", "mass"), ("cocg", "paper"), ("cocg", "jacobi"), ("cocr", "auto"),
+            ("tfqmr", "auto"), ("cgs", "auto"), ("bicgstab", "auto"), ("gmres", "auto")]
+    out = []
+    for f in (1e9, 10e9, 40e9):
+        for solver, diag in runs:
+            _, info = g.solve(2 * np.pi * f, src, tol=1e-8, solver=solver, diag=diag, max_iters=60000,
+                              raise_on_error=False)
+            out.append({"f_GHz": f / 1e9, "solver": solver, "diag": diag, "status": info["status_name"],
+                        "iterations": info["iterations"], "true_relres": info["true_relres"],
+                        "time_s": round(info["time_ms"] / 1e3, 2)})
+            _progress(f"solvers {f / 1e9:.0f} GHz {solver}/{diag}: {info['status_name']} "
+                      f"{info['iterations']} it, relres {info['true_relres']:.1e}")
+    return {"workload": "64x64x48-cell graded layered device (seed 12, 4 layers, 3 PEC strips, one "
+                        "port), 1/10/40 GHz, true relative residual 1e-8, cap 60k iterations",
+            "runs": out}
+
+
+def precision_row(fit, D, np, torch):
+    """The precision form on the 256x256x128 interconnect at 1, 10 and 40 GHz:
+    COCG in complex128 and the mixed form (complex64 inner iterations,
+    complex128 refinement), each capped at 100k iterations, with the mixed
+    result's forward error and port-voltage difference against the complex128
+    one.  Not part of the default run (about six minutes)."""
+    dev = D.interconnect_256(3)
+    if os.path.exists(TUNE_FILE):
+        fit.tune_load(TUNE_FILE)
+    g = fit.Grid(dev)
+    src = torch.from_numpy(D.port_source(dev, 0)).to("cuda:0")
+    out = []
+    for f in (1e9, 10e9, 40e9):
+        om = 2 * np.pi * f
+        x64, i64 = g.solve(om, src, tol=1e-8, solver="cocg", max_iters=100000, raise_on_error=False)
+        u64 = complex(g.port_voltages(x64)[0][0])
+        _progress(f"precision {f / 1e9:.0f} GHz complex128: {i64['status_name']} {i64['iterations']} it")
+        xm, im = g.solve(om, src, tol=1e-8, solver="cocg", precision="mixed", max_iters=100000,
+                         raise_on_error=False)
+        um = complex(g.port_voltages(xm)[0][0])
+        fe = (torch.linalg.vector_norm(xm - x64) / torch.linalg.vector_norm(x64)).item()
+        _progress(f"precision {f / 1e9:.0f} GHz mixed: {im['status_name']} {im['iterations']} it")
+        out.append({"f_GHz": f / 1e9,
+                    "c128": {"status": i64["status_name"], "iterations": i64["iterations"],
+                             "true_relres": i64["true_relres"], "time_s": round(i64["time_ms"] / 1e3, 2)},
+                    "mixed": {"status": im["status_name"], "iterations": im["iterations"],
+                              "refinements": im["refinements"], "fell_back": im["fell_back"],
+                              "true_relres": im["true_relres"], "time_s": round(im["time_ms"] / 1e3, 2)},
+                    "forward_error_mixed_vs_c128": fe,
+                    "port_voltage_rel_diff": abs(um - u64) / abs(u64) if u64 != 0 else None})
+        del x64, xm
+        torch.cuda.empty_cache()
+    return {"workload": "256x256x128-cell graded interconnect (seed 3), one port, 1/10/40 GHz, true "
+                        "relative residual 1e-8, cap 100k iterations", "runs": out}
+
+
+def family_row(fit, D, np, torch):
+    """The sweep over the six uneven sweep-family devices (64x64x32 to
+    192x192x96 cells, sigma strips, 4 ports), sampled: 8 of the 64
+    log-spaced frequencies over 1-40 GHz, port 1 excitation, complex128, cap
+    50k iterations, one fit_sweep per device after its shape tuning.  Not
+    part of the default run (about six minutes)."""
+    oms = D.log_spaced_omegas(64)[list(range(0, 64, 9))]
+    out = []
+    for dev in D.sweep_devices():
+        g = fit.Grid(dev)
+        batch, _ = g.autotune_sweep(oms, iters=100)
+        src = torch.from_numpy(D.port_source(dev, 0)).to("cuda:0")
+        t0 = time.perf_counter()
+        _, _, infos = fit.sweep([g], oms, [src[None, :]], tol=1e-8, max_iters=50000, precision="fp64")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = [k for k, i in enumerate(infos) if i["status"] == 0 and i["true_relres"] <= 1e-8]
+        its = [i["iterations"] for i in infos]
+        out.append({"device": dev.name, "cells": [dev.ncx, dev.ncy, dev.ncz], "unknowns": dev.n_edges,
+                    "systems_per_batch": batch, "tile": list(g.tile("c128")), "points": len(oms),
+                    "converged": len(ok), "wall_s": round(dt, 1), "iterations": [min(its), max(its)],
+                    "missed": [[round(oms[k] / 2 / np.pi / 1e9, 2), f"{infos[k]['true_relres']:.1e}"]
+                               for k in range(len(oms)) if k not in ok]})
+        _progress(f"family {dev.name}: {len(ok)}/{len(oms)} in {dt:.1f} s")
+        del g, src
+        torch.cuda.empty_cache()
+    return {"workload": "six sweep-family devices, 8 of 64 log-spaced frequencies 1-40 GHz, port 1, "
+                        "complex128 COCG, true relative residual 1e-8, cap 50k iterations", "devices": out}
+
+
 def _sweep_cpu_point(arg):
     """One sweep point of the oracle in a pool worker (one thread):
     assembly and scaling, 20 COCG iterations, extrapolated to `iters`."""
@@ -495,7 +591,8 @@ def main():
     ap.add_argument("--no-rows", action="store_true",
                     help="skip the secondary rows (256x256x128 interconnect, batched sweep, learned "
                          "preconditioner): only the bench grid runs")
-    ap.add_argument("--row", choices=["sweep", "precond", "interconnect", "baseline"],
+    ap.add_argument("--row", choices=["sweep", "precond", "interconnect", "baseline", "solvers",
+                                      "precision", "family"],
                     help="run only this secondary row and print it as one JSON line")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short sample profiled by the HBM-counter passes")
@@ -543,6 +640,12 @@ def main():
             row = interconnect_row(fit, D, np, torch, mean_us)
         elif args.row == "baseline":
             row = baseline_row(fit, D, np, torch)
+        elif args.row == "solvers":
+            row = solvers_row(fit, D, np, torch)
+        elif args.row == "precision":
+            row = precision_row(fit, D, np, torch)
+        elif args.row == "family":
+            row = family_row(fit, D, np, torch)
         else:
             fn = {"sweep": sweep_row, "precond": precond_row}[args.row]
             row = fn(fit, D, np, torch, not args.no_cpu_baseline)
