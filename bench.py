@@ -287,30 +287,97 @@ def _progress(msg):
     print(f"bench.py: {msg}", file=sys.stderr, flush=True)
 
 
-def solvers_row(fit, D, np, torch):
+def solvers_row(fit, D, np, torch, big=False):
     """Every method of the solver comparison on the 64x64x48-cell graded
-    layered device (4 layers, 3 PEC strips, one port, seed 12) at 1, 10 and
-    40 GHz to a true relative residual of 1e-8, capped at 60k iterations:
-    COCG with each diagonal, COCR, TFQMR, CGS, BiCGStab and GMRES(30).  Not
-    part of the default run (several minutes)."""
-    dev = D.layered_device(64, 64, 48, n_layers=4, n_strips=3, n_ports=1, seed=12)
+    layered device (4 layers, 3 PEC strips, one port, seed 12) -- or, with
+    big, on the 128^3-cell bench device (tile from the committed table) --
+    at 1, 10 and 40 GHz to a true relative residual of 1e-8, capped at 60k
+    iterations (GMRES(30) at 20k on the big device): COCG with each
+    diagonal, COCR, TFQMR, CGS, BiCGStab and GMRES(30).  Not part of the
+    default run (several minutes; about ten with big)."""
+    if big:
+        dev = D.plain_device_128(2)
+        if os.path.exists(TUNE_FILE):
+            fit.tune_load(TUNE_FILE)
+    else:
+        dev = D.layered_device(64, 64, 48, n_layers=4, n_strips=3, n_ports=1, seed=12)
     g = fit.Grid(dev)
     src = torch.from_numpy(D.port_source(dev, 0)).to("cuda:0")
     runs = [("cocg", "auto"), ("cocg", "mass"), ("cocg", "paper"), ("cocg", "jacobi"), ("cocr", "auto"),
             ("tfqmr", "auto"), ("cgs", "auto"), ("bicgstab", "auto"), ("gmres", "auto")]
+    if big:
+        runs.remove(("cocg", "mass"))  # the same iterates as auto, through the stored-diagonal path
     out = []
     for f in (1e9, 10e9, 40e9):
         for solver, diag in runs:
-            _, info = g.solve(2 * np.pi * f, src, tol=1e-8, solver=solver, diag=diag, max_iters=60000,
+            cap = 20000 if (big and solver == "gmres") else 60000
+            _, info = g.solve(2 * np.pi * f, src, tol=1e-8, solver=solver, diag=diag, max_iters=cap,
                               raise_on_error=False)
             out.append({"f_GHz": f / 1e9, "solver": solver, "diag": diag, "status": info["status_name"],
                         "iterations": info["iterations"], "true_relres": info["true_relres"],
                         "time_s": round(info["time_ms"] / 1e3, 2)})
             _progress(f"solvers {f / 1e9:.0f} GHz {solver}/{diag}: {info['status_name']} "
                       f"{info['iterations']} it, relres {info['true_relres']:.1e}")
-    return {"workload": "64x64x48-cell graded layered device (seed 12, 4 layers, 3 PEC strips, one "
-                        "port), 1/10/40 GHz, true relative residual 1e-8, cap 60k iterations",
+    name = ("128x128x128-cell graded layered device (seed 2, 6 layers, 4 PEC strips, one port)" if big
+            else "64x64x48-cell graded layered device (seed 12, 4 layers, 3 PEC strips, one port)")
+    return {"workload": name + ", 1/10/40 GHz, true relative residual 1e-8, cap 60k iterations"
+                        + (" (GMRES(30) 20k)" if big else ""),
             "runs": out}
+
+
+def learned_row(fit, D, np, torch):
+    """The learned form on the 192x192x96-cell family: the c = 16 U-Net
+    trained for 1,500 Adam steps on 8 solver pairs per (device, frequency)
+    from 8 seeded 64x64x32-cell family devices at 2, 10 and 30 GHz, then
+    FGMRES(30) with it (falling back to COCG on stagnation) against COCG and
+    GMRES(30) (cap 3,000) on the held-out devices 9000-9002 to 1e-8, and the
+    residual of FGMRES + U-Net and GMRES(30) after 300 steps.  Not part of
+    the default run (about ten minutes)."""
+    if os.path.exists(TUNE_FILE):
+        fit.tune_load(TUNE_FILE)
+    freqs = [2e9, 10e9, 30e9]
+    tg = [fit.Grid(D.learned_family_device(1000 + s, (64, 64, 32))) for s in range(8)]
+    t0 = time.perf_counter()
+    pre = fit.Precond.train(tg, [2 * np.pi * f for f in freqs], base_channels=16, steps=1500, batch=4,
+                            crop=32, seed=3, pairs_per_system=8, lr=1e-3)
+    torch.cuda.synchronize()
+    h = fit.Precond.train_history()
+    train = {"seconds": round(time.perf_counter() - t0, 1), "loss_first10": float(h[:10].mean()),
+             "loss_last50": float(h[-50:].mean())}
+    _progress(f"learned: trained in {train['seconds']} s, loss {train['loss_first10']:.3f} -> "
+              f"{train['loss_last50']:.3f}")
+    del tg
+    torch.cuda.empty_cache()
+    out = []
+    for seed in (9000, 9001, 9002):
+        dev = D.learned_family_device(seed)
+        g = fit.Grid(dev)
+        src = torch.from_numpy(D.port_source(dev, 0)).to("cuda:0")
+        for f in freqs:
+            om = 2 * np.pi * f
+            row = {"seed": seed, "f_GHz": f / 1e9}
+            for name, kw, cap in (("cocg", dict(solver="cocg"), 100000),
+                                  ("fgmres_unet", dict(solver="fgmres", precond=pre), 100000),
+                                  ("gmres30", dict(solver="gmres"), 3000)):
+                x, i = g.solve(om, src, tol=1e-8, max_iters=cap, raise_on_error=False, **kw)
+                row[name] = {"status": i["status_name"], "iterations": i["iterations"],
+                             "fell_back": i["fell_back"], "time_s": round(i["time_ms"] / 1e3, 2),
+                             "true_relres": i["true_relres"]}
+                del x
+            x, i = g.solve(om, src, tol=1e-8, max_iters=300, raise_on_error=False, solver="fgmres",
+                           precond=pre)
+            x2, i2 = g.solve(om, src, tol=1e-8, max_iters=300, raise_on_error=False, solver="gmres")
+            row["after_300"] = {"fgmres_unet": i["true_relres"], "gmres30": i2["true_relres"]}
+            del x, x2
+            out.append(row)
+            _progress(f"learned seed {seed} {f / 1e9:.0f} GHz: cocg {row['cocg']['iterations']} it, "
+                      f"fgmres+unet {row['fgmres_unet']['iterations']} it (fell back "
+                      f"{row['fgmres_unet']['fell_back']})")
+        del g, src
+        torch.cuda.empty_cache()
+    return {"workload": "c=16 U-Net trained on solver pairs from 8 64x64x32 family devices; held-out "
+                        "192x192x96 family devices 9000-9002 at 2/10/30 GHz, true relative residual 1e-8",
+            "training": train, "runs": out}
 
 
 def precision_row(fit, D, np, torch):
@@ -592,7 +659,7 @@ def main():
                     help="skip the secondary rows (256x256x128 interconnect, batched sweep, learned "
                          "preconditioner): only the bench grid runs")
     ap.add_argument("--row", choices=["sweep", "precond", "interconnect", "baseline", "solvers",
-                                      "precision", "family"],
+                                      "solvers128", "precision", "family", "learned"],
                     help="run only this secondary row and print it as one JSON line")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short sample profiled by the HBM-counter passes")
@@ -640,8 +707,10 @@ def main():
             row = interconnect_row(fit, D, np, torch, mean_us)
         elif args.row == "baseline":
             row = baseline_row(fit, D, np, torch)
-        elif args.row == "solvers":
-            row = solvers_row(fit, D, np, torch)
+        elif args.row in ("solvers", "solvers128"):
+            row = solvers_row(fit, D, np, torch, big=args.row == "solvers128")
+        elif args.row == "learned":
+            row = learned_row(fit, D, np, torch)
         elif args.row == "precision":
             row = precision_row(fit, D, np, torch)
         elif args.row == "family":
