@@ -774,3 +774,28 @@ def test_cgs_residual_is_the_squared_bicg_polynomial():
         poly_r, rr = poly_r_new, rr_new
         phis.append(np.linalg.norm(poly_r @ poly_r @ b) / np.linalg.norm(b))
     np.testing.assert_allclose(h, phis, rtol=1e-8)
+
+
+def test_graded_mesh_conditioning_rules_out_complex64_inner_solves():
+    """Why complex64 inner iterations stall on the graded meshes (the
+    precision form's evidence, Sec. III's scaled operator of eq. (e2t)): the
+    largest eigenvalue of S K S (S = M_eps^{-1/2}) relative to the shift
+    omega^2 bounds the condition number of S A S from below (its gradient
+    cluster sits at -omega^2).  At 1 GHz it exceeds 1/u32 on the graded
+    10-200 um mesh and stays two orders below it on a uniform 100 um mesh;
+    the ratio scales as omega^-2."""
+    import scipy.sparse.linalg as spla
+    u32 = 2.0 ** -24
+    ratio = {}
+    for graded in (True, False):
+        dev = D.layered_device(24, 24, 16, n_layers=4, n_strips=3, n_ports=1, seed=2, graded=graded)
+        f = O.free_edges(dev)
+        k = O.stiffness(dev)[f][:, f]
+        m_eps, _ = O.edge_materials(dev)
+        s = 1.0 / np.sqrt(m_eps[f].real)
+        sks = (sp.diags(s) @ k @ sp.diags(s)).tocsr()
+        lmax = spla.eigsh(sks, k=1, which="LA", return_eigenvectors=False)[0]
+        ratio[graded] = lmax / (2 * np.pi * 1e9) ** 2
+    assert ratio[True] * u32 > 1.0
+    assert ratio[False] * u32 < 0.1
+    assert ratio[True] > 50 * ratio[False]
