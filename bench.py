@@ -446,6 +446,47 @@ def family_row(fit, D, np, torch):
                         "complex128 COCG, true relative residual 1e-8, cap 50k iterations", "devices": out}
 
 
+def family_full_row(fit, D, np, torch):
+    """The sweep at full size on the two smallest sweep-family devices
+    (64x64x32 and 96x96x48 cells): all 64 log-spaced frequencies over
+    1-40 GHz times all 4 port excitations (256 systems each), complex128,
+    cap 50k iterations, in fit_sweep calls of 8 frequencies.  Not part of the
+    default run (about five minutes)."""
+    oms = D.log_spaced_omegas(64)
+    out = []
+    for dev in D.sweep_devices()[:2]:
+        g = fit.Grid(dev)
+        srcs = torch.stack([torch.from_numpy(D.port_source(dev, p)) for p in range(4)]).to("cuda:0")
+        batch, _ = g.autotune_sweep(oms[:16], iters=100)
+        ok, total, wall, its, missed = 0, 0, 0.0, [], []
+        for c in range(0, 64, 8):
+            o = oms[c:c + 8]
+            t0 = time.perf_counter()
+            _, _, infos = fit.sweep([g], o, [srcs], tol=1e-8, max_iters=50000, precision="fp64")
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            for k in range(len(o)):
+                for r in range(4):
+                    i = infos[k * 4 + r]
+                    total += 1
+                    its.append(i["iterations"])
+                    if i["status"] == 0 and i["true_relres"] <= 1e-8:
+                        ok += 1
+                    else:
+                        missed.append([round(o[k] / 2 / np.pi / 1e9, 2), r, f"{i['true_relres']:.1e}"])
+            _progress(f"family_full {dev.name}: {c + len(o)}/64 frequencies, {ok}/{total} at 1e-8")
+        out.append({"device": dev.name, "cells": [dev.ncx, dev.ncy, dev.ncz], "unknowns": dev.n_edges,
+                    "systems": total, "converged": ok, "systems_per_batch": batch,
+                    "tile": list(g.tile("c128")), "wall_s": round(wall, 1),
+                    "systems_per_s": round(ok / wall, 3), "iterations": [min(its), max(its)],
+                    "missed": missed})
+        del g, srcs
+        torch.cuda.empty_cache()
+    return {"workload": "64 log-spaced frequencies 1-40 GHz x 4 port excitations on the 64x64x32 and "
+                        "96x96x48 sweep-family devices, complex128 COCG, true relative residual 1e-8",
+            "devices": out}
+
+
 def _sweep_cpu_point(arg):
     """One sweep point of the oracle in a pool worker (one thread):
     assembly and scaling, 20 COCG iterations, extrapolated to `iters`."""
@@ -659,7 +700,7 @@ def main():
                     help="skip the secondary rows (256x256x128 interconnect, batched sweep, learned "
                          "preconditioner): only the bench grid runs")
     ap.add_argument("--row", choices=["sweep", "precond", "interconnect", "baseline", "solvers",
-                                      "solvers128", "precision", "family", "learned"],
+                                      "solvers128", "precision", "family", "family_full", "learned"],
                     help="run only this secondary row and print it as one JSON line")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short sample profiled by the HBM-counter passes")
@@ -715,6 +756,8 @@ def main():
             row = precision_row(fit, D, np, torch)
         elif args.row == "family":
             row = family_row(fit, D, np, torch)
+        elif args.row == "family_full":
+            row = family_full_row(fit, D, np, torch)
         else:
             fn = {"sweep": sweep_row, "precond": precond_row}[args.row]
             row = fn(fit, D, np, torch, not args.no_cpu_baseline)
