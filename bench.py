@@ -180,7 +180,7 @@ def sweep_row(fit, D, np, torch, with_cpu):
     # the sweep tuner's (chosen on batched launches) for the sweep.
     tile, _ = g.autotune_solver(float(oms[8]), iters=400)
     batch, _ = g.autotune_sweep(oms, iters=200)
-    sweep_tile = g.tile("c128")
+    sweep_tile = g.tile("c128_batched")
     src = torch.from_numpy(D.port_source(sd, 0)).to("cuda:0")
     fit.sweep([g], oms[:2], [src[None, :]], tol=1e-8)  # warm-up
     torch.cuda.synchronize()
@@ -188,9 +188,6 @@ def sweep_row(fit, D, np, torch, with_cpu):
     st, _, infos = fit.sweep([g], oms, [src[None, :]], tol=1e-8, precision="fp64")
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    g.set_tile("c128", *tile)
-    g.solve(float(oms[0]), src, tol=1e-8, solver="cocg", max_iters=40, raise_on_error=False)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for om in oms:
         g.solve(float(om), src, tol=1e-8, solver="cocg", raise_on_error=False)
@@ -238,15 +235,15 @@ def baseline_row(fit, D, np, torch):
     oms = D.log_spaced_omegas(64)
     src = torch.from_numpy(D.port_source(dev, 0)).to("cuda:0")
     # each side with its own tuned block shape: the solver tuner's for one
-    # system at a time, the sweep tuner's for the batched launches
+    # system at a time, the sweep tuner's (a tile-table key of its own) for
+    # the batched launches
     tile, _ = g.autotune_solver(float(oms[32]), iters=400)
     batch, _ = g.autotune_sweep(oms[:16], iters=200)
-    sweep_tile = g.tile("c128")
+    sweep_tile = g.tile("c128_batched")
     fit.sweep([g], oms[:2], [src[None, :]], tol=1e-8)  # warm-up
     torch.cuda.synchronize()
 
     def run_sweep(om_list, prec):
-        g.set_tile("c128", *sweep_tile)
         t0 = time.perf_counter()
         _, _, infos = fit.sweep([g], om_list, [src[None, :]], tol=1e-8, max_iters=60000, precision=prec)
         torch.cuda.synchronize()
@@ -254,7 +251,6 @@ def baseline_row(fit, D, np, torch):
         return time.perf_counter() - t0, ok
 
     full = {p: run_sweep(oms, p) for p in ("fp64", "mixed")}
-    g.set_tile("c128", *tile)
     conv, t_conv, t_all = [], 0.0, 0.0
     for k, om in enumerate(oms):
         torch.cuda.synchronize()
@@ -440,7 +436,7 @@ def family_row(fit, D, np, torch):
         ok = [k for k, i in enumerate(infos) if i["status"] == 0 and i["true_relres"] <= 1e-8]
         its = [i["iterations"] for i in infos]
         out.append({"device": dev.name, "cells": [dev.ncx, dev.ncy, dev.ncz], "unknowns": dev.n_edges,
-                    "systems_per_batch": batch, "tile": list(g.tile("c128")), "points": len(oms),
+                    "systems_per_batch": batch, "tile": list(g.tile("c128_batched")), "points": len(oms),
                     "converged": len(ok), "wall_s": round(dt, 1), "iterations": [min(its), max(its)],
                     "missed": [[round(oms[k] / 2 / np.pi / 1e9, 2), f"{infos[k]['true_relres']:.1e}"]
                                for k in range(len(oms)) if k not in ok]})
@@ -482,7 +478,7 @@ def family_full_row(fit, D, np, torch):
             _progress(f"family_full {dev.name}: {c + len(o)}/64 frequencies, {ok}/{total} at 1e-8")
         out.append({"device": dev.name, "cells": [dev.ncx, dev.ncy, dev.ncz], "unknowns": dev.n_edges,
                     "systems": total, "converged": ok, "systems_per_batch": batch,
-                    "tile": list(g.tile("c128")), "wall_s": round(wall, 1),
+                    "tile": list(g.tile("c128_batched")), "wall_s": round(wall, 1),
                     "systems_per_s": round(ok / wall, 3), "iterations": [min(its), max(its)],
                     "missed": missed})
         del g, srcs

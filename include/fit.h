@@ -60,6 +60,12 @@ typedef enum {
 
 typedef enum { FIT_C128 = 0, FIT_C64 = 1 } fit_dtype;
 
+/* Tile-table key of the block shape that batched (fit_sweep) launches use in
+ * complex128; fit_tile_set and fit_tile_get accept it in place of a dtype.
+ * Without an entry under this key the batched launches use the FIT_C128
+ * shape. */
+#define FIT_TILE_BATCHED_C128 2
+
 /* FIT_SCALE_NONE: y = A(omega) x, the operator of eq. (e2) with losses.
  * FIT_SCALE_SYM:  y = S A(omega) S x with S = diag(M_eps,c^{-1/2}),
  *   M_eps,c = M_eps - j M_sigma / omega: the symmetrically scaled operator of
@@ -337,13 +343,16 @@ fit_status fit_port_network(int nports, double z0, const double *zl, double *z_o
  * (48,8), (32,8), (32,16)}.  The table is process-wide and keyed by the
  * grid's node dimensions and dtype. */
 
-/* Force a tile shape for grids of g's node dimensions in `dtype`.
- * FIT_E_INVALID for a shape that is not compiled or zc outside [1, 128]. */
+/* Force a tile shape for grids of g's node dimensions in `dtype` (or under
+ * FIT_TILE_BATCHED_C128).  FIT_E_INVALID for a shape that is not compiled or
+ * zc outside [1, 128]. */
 fit_status fit_tile_set(const struct fit_grid *g, int dtype, int tx, int ty, int zc);
 
-/* The tile shape that launches on g in `dtype` use now (the table's entry
- * for its node dimensions, else the default shape).  FIT_E_INVALID for a
- * NULL grid or output pointer, or a bad dtype. */
+/* The tile shape that launches on g in `dtype` (or, with
+ * FIT_TILE_BATCHED_C128, batched complex128 launches) use now: the table's
+ * entry for its node dimensions, else the default shape (for the batched
+ * key: the FIT_C128 shape).  FIT_E_INVALID for a NULL grid or output
+ * pointer, or a bad dtype. */
 fit_status fit_tile_get(const struct fit_grid *g, int dtype, int32_t *tx, int32_t *ty, int32_t *zc);
 
 /* Time every compiled (TX, TY) with a range of ZC on g (operator in `dtype`
@@ -378,8 +387,9 @@ fit_status fit_sweep_set_batch(int systems);
  * free edge).  First the complex128 block shape: every compiled shape with
  * z-chunks of 4 and 8 planes on batches of up to 16 systems; the one with
  * the most system-iterations per second (a later one must win by more than
- * 2 %) is stored in the tile table for g's node dimensions, so later solves
- * on such grids use it too.  Then the systems per batch: 64, 32, 16, 8 and 4,
+ * 2 %) is stored under FIT_TILE_BATCHED_C128 for g's node dimensions (the
+ * shape of single solves is left alone).  Then the systems per batch: 64,
+ * 32, 16, 8 and 4,
  * from the largest down (a smaller batch must win by more than 2 %: fewer
  * batches leave fewer serial tails).  Sets the process-wide batch size;
  * reports it and its rate.  Synchronous. */

@@ -116,7 +116,7 @@ int zc_for(const fit_grid* g, int dtype, TileShape t) {
 int max_blocks_for(const fit_grid* g) {
   int mb = 8192;
   const TileShape shapes[] = {{64, 8, 0}, {48, 8, 0}, {32, 8, 0}, {32, 16, 0}};
-  for (int dt : {(int)FIT_C128, (int)FIT_C64}) {
+  for (int dt : {(int)FIT_C128, (int)FIT_C64, (int)FIT_TILE_BATCHED_C128}) {
     mb = std::max(mb, launch_blocks(make_launch(g->view, tile_for(g, dt), 1.0)));
     for (TileShape t : shapes) {
       t.zc = zc_for(g, dt, t);
@@ -178,7 +178,9 @@ struct Tables {
 // Builds and uploads the launch tables for the systems `act` (synchronous).
 template <class T>
 fit_status build_tables(std::vector<Sys*>& act, Tables<T>& t, void* dev_buf, hipStream_t s) {
-  const int dtype = sizeof(T) == 8 ? FIT_C128 : FIT_C64;
+  // tile-table key of the batched launches' block shape (complex128: the
+  // sweep tuner's own entry, else the single-system shape)
+  const int dtype = sizeof(T) == 8 ? FIT_TILE_BATCHED_C128 : FIT_C64;
   // one block shape for the launch: the largest grid's
   const Sys* big = act[0];
   for (Sys* y : act)
@@ -779,9 +781,10 @@ extern "C" fit_status fit_autotune_sweep(fit_grid* g, const double* omegas, int 
   // The complex128 block shape of the batched launches (every system of a
   // launch uses the largest grid's shape): the compiled shapes with z-chunks
   // of 4 and 8 planes, timed on batches of up to 16 systems; the best one is
-  // stored for the grid.  Shapes that suit one system at a time leave a
-  // batch of small grids too few workgroups per system.
-  const TileShape saved_tile = tile_for(g, FIT_C128);
+  // stored under the batched key for the grid's dimensions (single solves
+  // keep theirs).  Shapes that suit one system at a time leave a batch of
+  // small grids too few workgroups per system.
+  const TileShape saved_tile = tile_for(g, FIT_TILE_BATCHED_C128);
   TileShape best_t = saved_tile;
   double best_tr = -1.0;
   const TileShape cands[] = {{32, 16, 4}, {32, 16, 8}, {32, 8, 4}, {32, 8, 8},
@@ -789,7 +792,7 @@ extern "C" fit_status fit_autotune_sweep(fit_grid* g, const double* omegas, int 
   for (const TileShape& t : cands) {
     if (st != FIT_OK) break;
     if (t.zc > g->view.nz) continue;
-    if ((st = fit_tile_set(g, FIT_C128, t.tx, t.ty, t.zc)) != FIT_OK) break;
+    if ((st = fit_tile_set(g, FIT_TILE_BATCHED_C128, t.tx, t.ty, t.zc)) != FIT_OK) break;
     double rate = -1.0;
     if ((st = rate_of(16, &rate)) != FIT_OK) break;
     if (rate > 0.0 && (best_tr < 0.0 || rate > 1.02 * best_tr)) {
@@ -798,8 +801,9 @@ extern "C" fit_status fit_autotune_sweep(fit_grid* g, const double* omegas, int 
     }
   }
   {
-    const fit_status e = st == FIT_OK ? fit_tile_set(g, FIT_C128, best_t.tx, best_t.ty, best_t.zc)
-                                      : fit_tile_set(g, FIT_C128, saved_tile.tx, saved_tile.ty, saved_tile.zc);
+    const fit_status e = st == FIT_OK
+                             ? fit_tile_set(g, FIT_TILE_BATCHED_C128, best_t.tx, best_t.ty, best_t.zc)
+                             : fit_tile_set(g, FIT_TILE_BATCHED_C128, saved_tile.tx, saved_tile.ty, saved_tile.zc);
     if (st == FIT_OK) st = e;
   }
   // largest batch first: a smaller batch must be more than 2 % faster to

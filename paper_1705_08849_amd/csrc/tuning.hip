@@ -47,9 +47,13 @@ TileShape default_tile(const GridView& g, int dtype) {
 }
 
 TileShape tile_for(const fit_grid* g, int dtype) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tuned.find(std::make_tuple(g->view.nx, g->view.ny, g->view.nz, dtype));
-  if (it != g_tuned.end()) return it->second.t;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(g->view.nx, g->view.ny, g->view.nz, dtype));
+    if (it != g_tuned.end()) return it->second.t;
+  }
+  // batched launches without a shape of their own use the single-system one
+  if (dtype == FIT_TILE_BATCHED_C128) return tile_for(g, FIT_C128);
   return default_tile(g->view, dtype);
 }
 
@@ -90,7 +94,7 @@ static fit_status time_shape(const fit_grid* g, TileShape t, int scaling, double
 using namespace fit;
 
 extern "C" fit_status fit_tile_set(const fit_grid* g, int dtype, int tx, int ty, int zc) {
-  if (!g || (dtype != FIT_C128 && dtype != FIT_C64)) {
+  if (!g || (dtype != FIT_C128 && dtype != FIT_C64 && dtype != FIT_TILE_BATCHED_C128)) {
     set_error("fit_tile_set: NULL grid or bad dtype");
     return FIT_E_INVALID;
   }
@@ -104,7 +108,7 @@ extern "C" fit_status fit_tile_set(const fit_grid* g, int dtype, int tx, int ty,
 }
 
 extern "C" fit_status fit_tile_get(const fit_grid* g, int dtype, int32_t* tx, int32_t* ty, int32_t* zc) {
-  if (!g || !tx || !ty || !zc || (dtype != FIT_C128 && dtype != FIT_C64)) {
+  if (!g || !tx || !ty || !zc || (dtype != FIT_C128 && dtype != FIT_C64 && dtype != FIT_TILE_BATCHED_C128)) {
     set_error("fit_tile_get: NULL argument or bad dtype");
     return FIT_E_INVALID;
   }

@@ -32,6 +32,8 @@ SOLVERS = {"bicgstab": BICGSTAB, "gmres": GMRES, "fgmres": FGMRES, "cocg": COCG,
 SCALINGS = {"none": SCALE_NONE, "sym": SCALE_SYM, "fact": SCALE_FACT}
 PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
 DIAGS = {"auto": DIAG_AUTO, "mass": DIAG_MASS, "paper": DIAG_PAPER, "jacobi": DIAG_JACOBI}
+TILE_BATCHED_C128 = 2  # tile-table key of batched (sweep) launches in complex128
+_TILE_KEYS = {"c128": C128, "c64": C64, "c128_batched": TILE_BATCHED_C128}
 
 
 class FitError(RuntimeError):
@@ -260,20 +262,20 @@ class Grid:
 
     # -- launch shapes --------------------------------------------------------
     def set_tile(self, dtype: str, tx: int, ty: int, zc: int):
-        check(lib().fit_tile_set(self.h, {"c128": C128, "c64": C64}[dtype], tx, ty, zc),
+        check(lib().fit_tile_set(self.h, _TILE_KEYS[dtype], tx, ty, zc),
               "fit_tile_set")
 
     def tile(self, dtype: str = "c128"):
         """``fit_tile_get``: the (tx, ty, zc) that launches on this grid use now."""
         tx, ty, zc = C.c_int32(), C.c_int32(), C.c_int32()
-        check(lib().fit_tile_get(self.h, {"c128": C128, "c64": C64}[dtype], C.byref(tx), C.byref(ty),
+        check(lib().fit_tile_get(self.h, _TILE_KEYS[dtype], C.byref(tx), C.byref(ty),
                                  C.byref(zc)), "fit_tile_get")
         return tx.value, ty.value, zc.value
 
     def autotune(self, dtype: str = "c128", scaling: str = "none", omega: float = 2e10,
                  reps: int = 10, stream=None):
         tx, ty, zc, us = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
-        check(lib().fit_autotune(self.h, {"c128": C128, "c64": C64}[dtype], SCALINGS[scaling],
+        check(lib().fit_autotune(self.h, _TILE_KEYS[dtype], SCALINGS[scaling],
                                  float(omega), reps, _stream_ptr(stream), C.byref(tx),
                                  C.byref(ty), C.byref(zc), C.byref(us)), "fit_autotune")
         return (tx.value, ty.value, zc.value), us.value
