@@ -273,7 +273,10 @@ fit_status fit_solve(struct fit_grid *g, double omega, const void *source_dev, d
  * of the free device memory): each iteration of a batch is one operator
  * launch over all its systems' tiles, one streaming update launch and two
  * small finish launches, replayed from a captured hipGraph; converged
- * systems drop out at once.  The method is the mass-preconditioned COCG of
+ * systems drop out at once.  The systems of a launch share the largest
+ * grid's block shape (complex128: its FIT_TILE_BATCHED_C128 entry if there
+ * is one, see fit_autotune_sweep) with their own z-chunks; the batch size is
+ * fit_sweep_set_batch's.  The method is the mass-preconditioned COCG of
  * fit_solve (opts->solver must be FIT_COCG, else FIT_E_UNSUPPORTED);
  * opts->precision FIT_PREC_FP64 iterates in complex128, FIT_PREC_MIXED in
  * complex64 with complex128 refinement and a complex128 finish for systems
